@@ -1,0 +1,209 @@
+"""Seeded synthetic workloads for the axisymmetric cascaded LB time step.
+
+This module only builds inputs: case geometry, boundary settings, transport
+coefficients chosen from the dimensionless groups of the paper's Section 3
+problems, and seeded initial fields.  It holds none of the method's
+arithmetic, and it is the one module that both the HIP library's callers and
+the oracle's callers use.
+
+Random numbers come from splitmix64 (Steele, Lea & Flood, 2014), a
+counter-based generator: value k of a stream with seed s is the 64-bit mix
+of s + (k + 1) * 0x9E3779B97F4A7C15, mapped to a double in [0, 1) by its top
+53 bits.
+
+A case is a plain dict:
+  Nr, Nz            fluid nodes along r (y) and z (x)
+  cylinder          1 = solid cylinder with the axis at y = 0, 0 = annulus
+  r_inner           annulus inner-wall radius (lattice units)
+  nu, alpha         kinematic viscosity and thermal diffusivity
+  Pr, Ra            Prandtl and Rayleigh numbers (Ra uses L = Nr, dT = 1)
+  g_axial, T0       uniform axial body force, Boussinesq reference T
+  omega3            bulk-viscosity rate (the higher-order rates default to 1)
+  bc                {(face, field): (kind, value)}
+  T_ref             reference temperature about which h is stored on the GPU
+  fields            callable () -> dict of initial host fields [iz][ir]
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Faces, distributions and boundary kinds (numbering of the C interface).
+R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
+FLOW, SWIRL, THERMAL = 0, 1, 2
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC = 0, 1, 2, 3, 4, 5
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, n: int, offset: int = 0) -> np.ndarray:
+    """n raw 64-bit outputs of the splitmix64 stream `seed`, from `offset`."""
+    k = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + k * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform(seed: int, n: int, offset: int = 0) -> np.ndarray:
+    """n doubles in [0, 1) from the top 53 bits of splitmix64."""
+    return (splitmix64(seed, n, offset) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+# ------------------------------------------------------------------ helpers
+def _walls(bc, face, inner_swirl=(NOSLIP, 0.0), thermal=(ADIABATIC, 0.0)):
+    bc[(face, FLOW)] = (NOSLIP, 0.0)
+    bc[(face, SWIRL)] = inner_swirl
+    bc[(face, THERMAL)] = thermal
+
+
+def _periodic_z(bc):
+    for face in (Z_LO, Z_HI):
+        for fld in (FLOW, SWIRL, THERMAL):
+            bc[(face, fld)] = (PERIODIC, 0.0)
+
+
+def _axis(bc):
+    for fld in (FLOW, SWIRL, THERMAL):
+        bc[(R_IN, fld)] = (MIRROR, 0.0)
+
+
+def convection_velocity_scale_params(L: float, Pr: float, Ra: float, U: float = 0.05,
+                                     floor: float = 1.0 / 300.0):
+    """nu, alpha for a buoyancy velocity scale sqrt(g beta dT L) = U (kept
+    small, Section 3.2): nu = U L sqrt(Pr/Ra), alpha = nu/Pr.  Coefficients
+    are floored at `floor` (relaxation time 0.51); the effective Ra is then
+    recomputed from g beta = U^2/L and returned."""
+    nu = U * L * math.sqrt(Pr / Ra)
+    alpha = nu / Pr
+    if nu < floor or alpha < floor:
+        scale = max(floor / nu, floor / alpha)
+        nu, alpha = nu * scale, alpha * scale
+    gbeta = U * U / L
+    Ra_eff = gbeta * L ** 3 / (nu * alpha)
+    return nu, alpha, Ra_eff
+
+
+def _perturbed_T(seed: int, Nz: int, Nr: int, base: float = 0.5, amp: float = 1e-4):
+    def make():
+        T = base + amp * (2.0 * uniform(seed, Nz * Nr) - 1.0)
+        return {"T": T.reshape(Nz, Nr)}
+    return make
+
+
+# ------------------------------------------------------------------ cases
+def couette_poiseuille_conduction(Nr: int = 30, Nz: int = 8, r_inner: float = 10.0,
+                                  u_wall: float = 1e-3, g: float = 1e-6,
+                                  nu: float = 0.1, alpha: float = 0.1) -> dict:
+    """Annulus between coaxial cylinders, periodic along z: an axial body
+    force drives annular Poiseuille flow, the inner wall turns (circular
+    Couette flow in u_theta) and is hot (T = 1) against a cold outer wall
+    (T = 0), no buoyancy (Section 3.1 geometry).  Nr counts fluid rows; the
+    half-way walls sit at r_inner and r_inner + Nr."""
+    bc = {}
+    _walls(bc, R_IN, (DIRICHLET, u_wall), (DIRICHLET, 1.0))
+    _walls(bc, R_OUT, (DIRICHLET, 0.0), (DIRICHLET, 0.0))
+    _periodic_z(bc)
+    return dict(name="couette_poiseuille_conduction", Nr=Nr, Nz=Nz, cylinder=0,
+                r_inner=float(r_inner), nu=nu, alpha=alpha, Pr=nu / alpha, Ra=0.0,
+                g_axial=g, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5,
+                fields=lambda: {"T": np.full((Nz, Nr), 0.5)})
+
+
+def annulus_convection(Nr: int = 256, Nz: int = 256, radius_ratio: float = 2.0,
+                       Pr: float = 0.71, Ra: float = 1e5, seed: int = 1,
+                       U: float = 0.05) -> dict:
+    """Buoyant natural convection in a vertical annulus (Section 3.2): hot
+    inner wall T = 1, cold outer wall T = 0, adiabatic no-slip lids, gravity
+    along -z.  L = R_o - R_i = Nr, R_o/R_i = radius_ratio.  Initial state at
+    rest with T = 0.5 + seeded uniform noise of amplitude 1e-4."""
+    r_inner = Nr / (radius_ratio - 1.0)
+    nu, alpha, Ra_eff = convection_velocity_scale_params(Nr, Pr, Ra, U)
+    bc = {}
+    _walls(bc, R_IN, (NOSLIP, 0.0), (DIRICHLET, 1.0))
+    _walls(bc, R_OUT, (NOSLIP, 0.0), (DIRICHLET, 0.0))
+    _walls(bc, Z_LO)
+    _walls(bc, Z_HI)
+    return dict(name="annulus_convection", Nr=Nr, Nz=Nz, cylinder=0, r_inner=r_inner,
+                nu=nu, alpha=alpha, Pr=nu / alpha, Ra=Ra_eff, g_axial=0.0, T0=0.5,
+                omega3=1.0, bc=bc, T_ref=0.5, seed=seed,
+                fields=_perturbed_T(seed, Nz, Nr))
+
+
+def rotating_lid_cylinder(Nr: int = 1024, Nz: int = 2048, Re: float = 1000.0,
+                          Ri: float = 0.5, Pr: float = 1.0, u_lid: float = 0.05,
+                          seed: int = 3) -> dict:
+    """Closed cylinder H = Nz, R = Nr with a rotating bottom lid (u_theta =
+    Omega r, Omega R = u_lid), Re = Omega R^2 / nu, axial temperature
+    difference (top T = 1, bottom T = 0, adiabatic side wall) with
+    Richardson number Ri = g beta dT R / (Omega R)^2, Pr = nu / alpha
+    (Section 3.4 geometry with the buoyancy of Section 3.3).  The axis uses
+    the mirror condition."""
+    R = float(Nr)
+    Omega = u_lid / R
+    nu = u_lid * R / Re
+    alpha = nu / Pr
+    gbeta = Ri * u_lid * u_lid / R
+    Ra = gbeta * R ** 3 / (nu * alpha)
+    bc = {}
+    _axis(bc)
+    _walls(bc, R_OUT, (NOSLIP, 0.0), (ADIABATIC, 0.0))
+    _walls(bc, Z_LO, (OMEGA_R, Omega), (DIRICHLET, 0.0))
+    _walls(bc, Z_HI, (NOSLIP, 0.0), (DIRICHLET, 1.0))
+    return dict(name="rotating_lid_cylinder", Nr=Nr, Nz=Nz, cylinder=1, r_inner=0.0,
+                nu=nu, alpha=alpha, Pr=Pr, Ra=Ra, Re=Re, Ri=Ri, Omega=Omega,
+                g_axial=0.0, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5, seed=seed,
+                fields=_perturbed_T(seed, Nz, Nr))
+
+
+def batched_annuli(n: int = 256, seed: int = 4):
+    """Uneven annulus convection instances: Nr ~ U{48..256}, Nz ~ U{48..512},
+    Ra log-uniform in [1e3, 1e6], Pr log-uniform in [0.02, 7], radius ratio
+    uniform in [1.5, 4]; instance k uses seed*1000 + k for its noise."""
+    u = uniform(seed, 5 * n).reshape(n, 5)
+    cases = []
+    for k in range(n):
+        Nr = 48 + int(u[k, 0] * (256 - 48 + 1))
+        Nz = 48 + int(u[k, 1] * (512 - 48 + 1))
+        Ra = 10.0 ** (3.0 + 3.0 * u[k, 2])
+        Pr = 10.0 ** (math.log10(0.02) + (math.log10(7.0) - math.log10(0.02)) * u[k, 3])
+        ratio = 1.5 + 2.5 * u[k, 4]
+        c = annulus_convection(Nr=Nr, Nz=Nz, radius_ratio=ratio, Pr=Pr, Ra=Ra,
+                               seed=seed * 1000 + k)
+        c["name"] = "batched_annulus_%d" % k
+        cases.append(c)
+    return cases
+
+
+def serving_trace(n: int = 2000, rate: float = 200.0, seed: int = 5,
+                  max_nr_log2: float = 10.0, max_nz_log2: float = 11.0):
+    """Poisson arrivals at `rate` per second of solve requests mixing the
+    three problem types, grids N_r = 2^U(6, max_nr_log2), N_z = 2^U(6,
+    max_nz_log2) rounded to multiples of 16, storage FP32 or 16-bit with
+    probability 1/2 each.  Returns a list of (arrival_s, case, storage)."""
+    u = uniform(seed, 6 * n).reshape(n, 6)
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += -math.log(1.0 - u[k, 0]) / rate
+        kind = min(int(u[k, 1] * 3), 2)
+        Nr = int(round(2.0 ** (6 + (max_nr_log2 - 6) * u[k, 2]) / 16.0)) * 16
+        Nz = int(round(2.0 ** (6 + (max_nz_log2 - 6) * u[k, 3]) / 16.0)) * 16
+        Nr, Nz = max(Nr, 16), max(Nz, 16)
+        storage = "f32" if u[k, 4] < 0.5 else "f16"
+        if kind == 0:
+            c = couette_poiseuille_conduction(Nr=Nr, Nz=Nz, r_inner=Nr / 3.0)
+        elif kind == 1:
+            c = annulus_convection(Nr=Nr, Nz=Nz, Ra=10.0 ** (3 + 2 * u[k, 5]),
+                                   seed=seed * 100000 + k)
+        else:
+            c = rotating_lid_cylinder(Nr=Nr, Nz=Nz, Re=200.0 + 300.0 * u[k, 5],
+                                      seed=seed * 100000 + k)
+        c["name"] = "request_%d" % k
+        out.append((t, c, storage))
+    return out
