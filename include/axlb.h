@@ -1,0 +1,187 @@
+/*
+ * axlb: the time step of the axisymmetric cascaded central-moment lattice
+ * Boltzmann method for thermal flows with swirl (Hajabdollahi, Premnath &
+ * Welch, arXiv 1806.10241, Section 2) on AMD Instinct MI355X (gfx950).
+ *
+ * One lattice is the meridian plane of an annulus (R_i <= r <= R_i + Nr) or
+ * of a solid cylinder (0 <= r <= Nr) with Nz nodes along the axis, in
+ * lattice units (dx = dt = 1).  Each node carries the three distribution
+ * functions of the paper: a D2Q9 f for rho, u_z, u_r (Section 2.2), a D2Q5 g
+ * for psi = rho u_theta (Section 2.3) and a D2Q5 h for T (Section 2.4).
+ * One call of axlb_step advances all of them by the symmetric split scheme
+ * of eq. (20), (37) and (45): streaming, pre-collision half source step
+ * (eq. 21, 38, 48), cascaded collision (eq. 17, 34, 49), post-collision
+ * source moments (eq. 26, 41, 51), with the geometric sources of eq. (4),
+ * (7), (9) and the body force of eq. (5).
+ *
+ * Conventions shared by every call:
+ *  - Status: functions return AXLB_OK (0) or a negative AXLB_E* code; no
+ *    exception crosses this interface; axlb_last_error() gives the message.
+ *  - Host field arrays are FP64, length Nz*Nr, layout [iz][ir] (r fastest),
+ *    owned by the caller.  Device state is owned by the library.
+ *  - Coordinates: z (axial, index iz) is the paper's x, r (radial, index ir)
+ *    its y.  Nodes sit half a spacing from walls and from the axis:
+ *    r = r0 + ir + 1/2 with r0 = R_i (annulus) or 0 (cylinder).
+ *  - Ordering: axlb_step is asynchronous on the lattice's HIP stream; calls
+ *    that return host data (get_moments, nusselt, residual, save) wait for
+ *    that stream.  One lattice must not be used from two threads at once;
+ *    different lattices are independent.
+ */
+#ifndef AXLB_H
+#define AXLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define AXLB_OK 0
+#define AXLB_EINVAL (-1)    /* bad argument: sizes, tau <= 1/2, Pr != nu/alpha, BC mix */
+#define AXLB_ENOMEM (-2)    /* device memory or the pool's memory budget exhausted     */
+#define AXLB_EUNSTABLE (-3) /* a non-finite value was found in the state               */
+#define AXLB_EDEVICE (-4)   /* a HIP runtime call failed                               */
+#define AXLB_ESTATE (-5)    /* call not valid in the current state                     */
+
+/* ---- population storage (Section 2; FP32 arithmetic in every case) ---- */
+#define AXLB_F32 0   /* 4 bytes per population, 152 B per node update         */
+#define AXLB_F16 1   /* IEEE binary16, round to nearest even, 76 B per update  */
+#define AXLB_BF16 2  /* bfloat16, round to nearest even, 76 B per update       */
+
+/* ---- streaming layouts ---- */
+#define AXLB_LAYOUT_AA 0 /* one population buffer, in place, alternating phases */
+#define AXLB_LAYOUT_AB 1 /* two population buffers, pull streaming              */
+
+/* ---- geometry ---- */
+#define AXLB_ANNULUS 0  /* fluid between r = R_i and r = R_i + Nr            */
+#define AXLB_CYLINDER 1 /* fluid between the axis r = 0 and r = Nr           */
+
+/* ---- faces, distribution functions and boundary kinds ---- */
+#define AXLB_R_IN 0  /* inner cylinder wall, or the axis of a cylinder */
+#define AXLB_R_OUT 1
+#define AXLB_Z_LO 2
+#define AXLB_Z_HI 3
+
+#define AXLB_FLOW 0    /* f: rho, u_z, u_r   */
+#define AXLB_SWIRL 1   /* g: psi = rho u_theta */
+#define AXLB_THERMAL 2 /* h: T               */
+
+#define AXLB_NOSLIP 0    /* wall at rest for f (half-way bounce-back); for g: u_theta = 0 */
+#define AXLB_PERIODIC 1  /* z faces only, set for all fields on both z faces           */
+#define AXLB_MIRROR 2    /* the axis of a cylinder (set automatically, all fields)      */
+#define AXLB_DIRICHLET 3 /* g: imposed u_theta = value; h: imposed T = value            */
+#define AXLB_OMEGA_R 4   /* g: u_theta = Omega * r at the wall, Omega = value (NaN: the
+                            lattice's Omega)                                            */
+#define AXLB_ADIABATIC 5 /* h (or g): zero normal flux                                  */
+
+typedef struct axlb_lattice axlb_lattice;
+
+typedef struct {
+    int kind;       /* AXLB_ANNULUS or AXLB_CYLINDER                      */
+    double r_inner; /* annulus inner radius R_i > 0 (ignored for cylinder) */
+} axlb_geometry;
+
+/* Relaxation rates the transport coefficients leave free (text after
+ * eq. 17, 34, 49).  omega_4 = omega_5 and omega^psi_{1,2} follow from nu,
+ * omega^phi_{1,2} from alpha.  NULL selects omega3 = 1 and all others 1. */
+typedef struct {
+    double omega3;                 /* bulk viscosity xi = (1/omega3 - 1/2)/3 */
+    double omega6, omega7, omega8; /* third and fourth order, D2Q9           */
+    double omega_psi3, omega_psi4; /* second order, D2Q5 for psi             */
+    double omega_phi3, omega_phi4; /* second order, D2Q5 for T               */
+} axlb_relax;
+
+typedef struct {
+    int storage;  /* AXLB_F32 | AXLB_F16 | AXLB_BF16                         */
+    int layout;   /* AXLB_LAYOUT_AA (default) | AXLB_LAYOUT_AB                */
+    double T_ref; /* temperature about which h is stored (shifted storage)   */
+    void *stream; /* hipStream_t to run on; NULL: the library makes its own  */
+    int device;   /* HIP device ordinal; -1: the current device              */
+    void *device_buf;    /* optional caller-owned device memory of at least
+                            axlb_state_bytes() bytes, 256-byte aligned, that
+                            must outlive the lattice; NULL: the library
+                            allocates (and frees) its own                   */
+    size_t device_bytes; /* size of device_buf                              */
+} axlb_options;
+
+/* Bytes of device memory a lattice of this size holds (populations, lagged
+ * derivative fields and reduction scratch). */
+int axlb_state_bytes(int Nr, int Nz, int storage, int layout, size_t *bytes);
+
+/* Creates a lattice at rest (rho = 1, u = 0, T = T_ref).
+ *  Nr, Nz  fluid nodes along r and z (Nr >= 2, Nz >= 1; Nz >= 2 unless z is
+ *          periodic).
+ *  nu      kinematic viscosity; omega_4,5 = omega^psi_1,2 = 1/(3 nu + 1/2)
+ *          (text after eq. 17 and eq. 34); nu > 0 (tau > 1/2).
+ *  alpha   thermal diffusivity; omega^phi_1,2 = 1/(3 alpha + 1/2) (after
+ *          eq. 49); alpha > 0.
+ *  Pr      Prandtl number, checked against nu/alpha to 1e-9 relative
+ *          (0: not checked).
+ *  Ra      Rayleigh number (Section 3.2) with L = Nr and dT = 1:
+ *          g beta = Ra nu alpha / Nr^3; the buoyancy force is
+ *          g beta (T - T0) along +z (eq. 5, F^b_x).
+ *  Omega   angular velocity of OMEGA_R faces set with value NaN.
+ *  w       relaxation rates (NULL: defaults); opt: storage/layout/stream
+ *          (NULL: FP32, AA, T_ref = 0.5, own stream, current device).
+ * Defaults: every face a no-slip wall with u_theta = 0 and zero heat flux;
+ * a cylinder's inner face is the axis.  *out receives the handle. */
+int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, double alpha,
+                        double Pr, double Ra, double Omega, const axlb_relax *w,
+                        const axlb_options *opt, axlb_lattice **out);
+
+/* Boundary rule of one distribution function on one face (Section 3.1 to
+ * 3.4: half-way bounce-back for no-slip, the advection-diffusion wall
+ * rule for imposed u_theta or T and zero flux, the axis mirror, periodic
+ * z).  Only before the first step; AXLB_ESTATE afterwards. */
+int axlb_set_bc(axlb_lattice *lat, int face, int field, int kind, double value);
+
+/* Axial body force per unit mass g_axial and Boussinesq reference T0
+ * (eq. 5: F^b_x = g_axial + g beta (T - T0)).  Only before the first step. */
+int axlb_set_body_force(axlb_lattice *lat, double g_axial, double T0);
+
+/* Resets the state to the equilibria of the given host fields (any may be
+ * NULL: rho = 1, velocities 0, T = T_ref); step count returns to 0. */
+int axlb_set_fields(axlb_lattice *lat, const double *rho, const double *ur, const double *uz,
+                    const double *uth, const double *T);
+
+/* Enqueues n time steps on the lattice's stream (asynchronous). */
+int axlb_step(axlb_lattice *lat, long n);
+long axlb_steps_done(const axlb_lattice *lat);
+/* Waits for the lattice's stream. */
+int axlb_sync(axlb_lattice *lat);
+
+/* Fields the next step's collision sees (after the pre-collision half
+ * source step, eq. 21, 38, 48): rho, u_r, u_z, u_theta = psi/rho, T.
+ * Any pointer may be NULL.  Synchronous. */
+int axlb_get_moments(axlb_lattice *lat, double *rho, double *ur, double *uz, double *uth,
+                     double *T);
+
+/* Wall Nusselt numbers (Section 3.2), FP64 reduction on the device.
+ * Annulus: a = Nu_i at R_i, b = Nu_o at R_o (both r walls must impose T).
+ * Cylinder: a, b = bottom and top lid (both z walls must impose T).
+ * mean = (a + b)/2.  Synchronous. */
+int axlb_nusselt(axlb_lattice *lat, double *nu_a, double *nu_b, double *mean);
+
+/* Convergence residual, FP64 on the device: the largest over u_z, u_r,
+ * u_theta, T of ||q_now - q_then||_2 / (K ||q_now||_2), q_then being the
+ * fields at the previous call and K the steps in between (fields with zero
+ * norm are skipped).  The first call only records the fields and returns
+ * +inf.  AXLB_EUNSTABLE if a non-finite value is found.  Synchronous. */
+int axlb_residual(axlb_lattice *lat, double *r);
+
+/* Checkpoint: the whole state (populations, lagged fields, phase, step
+ * count) as an opaque byte image in caller memory.  Synchronous. */
+int axlb_state_size(const axlb_lattice *lat, size_t *bytes);
+int axlb_save(axlb_lattice *lat, void *host, size_t bytes);
+int axlb_load(axlb_lattice *lat, const void *host, size_t bytes);
+
+void axlb_destroy(axlb_lattice *lat);
+/* Message of the last failed call on lat (or of the last failed create when
+ * lat is NULL).  Valid until the next call on lat. */
+const char *axlb_last_error(const axlb_lattice *lat);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,571 @@
+// C-ABI of the axisymmetric cascaded LB step (include/axlb.h): parameter
+// validation, device memory, step scheduling with HIP graph bundles,
+// reductions and checkpoints.  No exception crosses the interface.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/axlb.h"
+#include "axlb_internal.h"
+#include "axlb_launch.h"
+
+using namespace axlb;
+
+static thread_local std::string g_create_error;
+
+namespace axlb {
+
+size_t storage_size(int storage) { return storage == AXLB_F32 ? 4 : 2; }
+
+Layout layout_for(int Nr, int Nz, int storage, int layout) {
+    Layout L;
+    L.pitch = ((Nr + 63) / 64) * 64;
+    L.plane = (long long)Nz * L.pitch;
+    const size_t a = 256;
+    auto up = [&](size_t b) { return (b + a - 1) / a * a; };
+    L.pop_bytes = up((size_t)NPOP * L.plane * storage_size(storage));
+    L.lag_bytes = up((size_t)NLAG * L.plane * sizeof(float));
+    const size_t N = (size_t)Nr * Nz;
+    L.fld_bytes = up(5 * N * sizeof(double));
+    L.snap_bytes = up(4 * N * sizeof(double));
+    L.red_bytes = up((RED_BLOCKS * 9 + 16) * sizeof(double));
+    L.total = (layout == AXLB_LAYOUT_AB ? 2 : 1) * L.pop_bytes + 2 * L.lag_bytes + L.fld_bytes +
+              L.snap_bytes + L.red_bytes;
+    return L;
+}
+
+}  // namespace axlb
+
+#define HIP_TRY(lat, expr)                                                        \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) return fail(lat, AXLB_EDEVICE, std::string(#expr) + \
+                                                                 ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static int fail(axlb_lattice *lat, int code, const std::string &msg) {
+    if (lat) lat->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+static bool is_wall(int k) {
+    return k == AXLB_NOSLIP || k == AXLB_DIRICHLET || k == AXLB_OMEGA_R || k == AXLB_ADIABATIC;
+}
+
+static bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
+
+// Device parameters of a lattice.
+KParams axlb::make_params(const axlb_lattice *L) {
+    KParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.Nr = L->Nr;
+    P.Nz = L->Nz;
+    P.pitch = L->lay.pitch;
+    P.plane = L->lay.plane;
+    P.r0 = (float)(L->cylinder ? 0.0 : L->r_inner);
+    P.nu = (float)L->nu;
+    P.alpha = (float)L->alpha;
+    P.g_axial = (float)L->g_axial;
+    P.gbeta = (float)L->gbeta;
+    P.T0 = (float)L->T0;
+    P.Tref = (float)L->T_ref;
+    // nu = c_s^2 (1/omega - 1/2), c_s^2 = 1/3 (text after eq. 17, 34, 49)
+    P.om3 = (float)L->relax.omega3;
+    P.om45 = (float)(1.0 / (3.0 * L->nu + 0.5));
+    P.om6 = (float)L->relax.omega6;
+    P.om7 = (float)L->relax.omega7;
+    P.om8 = (float)L->relax.omega8;
+    P.og12 = (float)(1.0 / (3.0 * L->nu + 0.5));
+    P.og3 = (float)L->relax.omega_psi3;
+    P.og4 = (float)L->relax.omega_psi4;
+    P.oh12 = (float)(1.0 / (3.0 * L->alpha + 0.5));
+    P.oh3 = (float)L->relax.omega_phi3;
+    P.oh4 = (float)L->relax.omega_phi4;
+    P.kinds = 0;
+    for (int f = 0; f < 4; ++f)
+        for (int d = 0; d < 3; ++d) {
+            P.kinds |= (unsigned long long)(L->kind[f][d] & 15) << (4 * (3 * f + d));
+            double v = L->val[f][d];
+            if (L->kind[f][d] == AXLB_OMEGA_R && std::isnan(v)) v = L->Omega;
+            P.val[f][d] = (float)v;
+        }
+    return P;
+}
+
+// Boundary settings that the step kernels can execute.
+static int check_bcs(axlb_lattice *L) {
+    for (int d = 0; d < 3; ++d) {
+        const bool plo = L->kind[AXLB_Z_LO][d] == AXLB_PERIODIC;
+        const bool phi = L->kind[AXLB_Z_HI][d] == AXLB_PERIODIC;
+        if (plo != phi) return fail(L, AXLB_EINVAL, "periodic z must be set on both z faces");
+        if (!plo && L->Nz < 2) return fail(L, AXLB_EINVAL, "Nz >= 2 needed with walls along z");
+    }
+    for (int f = 0; f < 4; ++f) {
+        const bool w = is_wall(L->kind[f][0]);
+        const bool p = L->kind[f][0] == AXLB_PERIODIC;
+        for (int d = 1; d < 3; ++d) {
+            if (is_wall(L->kind[f][d]) != w || (L->kind[f][d] == AXLB_PERIODIC) != p)
+                return fail(L, AXLB_EINVAL,
+                            "a face must be a wall, periodic or the axis for all three fields");
+        }
+    }
+    return AXLB_OK;
+}
+
+// HIP graph of BUNDLE consecutive steps starting at an even (k = 0) or odd
+// (k = 1) step count; BUNDLE is even, so every buffer role recurs.
+static int launch_one(axlb_lattice *L, long t) {
+    const KParams &P = L->P;
+    const int par = (int)(t & 1);
+    float *Mprev = L->lag[par], *Mnext = L->lag[par ^ 1];
+    hipError_t e;
+    if (L->layout == AXLB_LAYOUT_AA)
+        e = launch_step(P, L->storage, par == 0 ? 1 : 2, L->pop[0], L->pop[0], Mprev, Mnext,
+                        L->stream);
+    else
+        e = launch_step(P, L->storage, 0, L->pop[par], L->pop[par ^ 1], Mprev, Mnext, L->stream);
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return AXLB_OK;
+}
+
+static int ensure_graph(axlb_lattice *L, int k) {
+    if (L->graph_exec[k]) return AXLB_OK;
+    HIP_TRY(L, hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
+    int rc = AXLB_OK;
+    for (long s = 0; s < BUNDLE && rc == AXLB_OK; ++s) rc = launch_one(L, k + s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(L->stream, &g);
+    if (rc != AXLB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&L->graph_exec[k], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        L->graph_exec[k] = nullptr;
+        return fail(L, AXLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return AXLB_OK;
+}
+
+static int set_device(axlb_lattice *L) {
+    HIP_TRY(L, hipSetDevice(L->device));
+    return AXLB_OK;
+}
+
+// Fields of the current state into L->fld (device, FP64 planes rho, u_r,
+// u_z, u_theta, T).
+static int compute_fields(axlb_lattice *L) {
+    const long t = L->steps;
+    const int par = (int)(t & 1);
+    hipError_t e;
+    if (L->layout == AXLB_LAYOUT_AA)
+        e = launch_fields(L->P, L->storage, par == 0 ? 1 : 2, L->pop[0], L->lag[par], L->fld,
+                          L->stream);
+    else
+        e = launch_fields(L->P, L->storage, 0, L->pop[par], L->lag[par], L->fld, L->stream);
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("fields launch: ") + hipGetErrorString(e));
+    return AXLB_OK;
+}
+
+extern "C" {
+
+int axlb_state_bytes(int Nr, int Nz, int storage, int layout, size_t *bytes) {
+    if (!bytes || Nr < 2 || Nz < 1 || storage < 0 || storage > 2 || layout < 0 || layout > 1)
+        return fail(nullptr, AXLB_EINVAL, "axlb_state_bytes: bad arguments");
+    *bytes = layout_for(Nr, Nz, storage, layout).total;
+    return AXLB_OK;
+}
+
+int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, double alpha,
+                        double Pr, double Ra, double Omega, const axlb_relax *w,
+                        const axlb_options *opt, axlb_lattice **out) {
+    if (!out) return fail(nullptr, AXLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!geo) return fail(nullptr, AXLB_EINVAL, "geometry is NULL");
+    if (Nr < 2 || Nz < 1 || (long long)Nr * Nz > (1LL << 31))
+        return fail(nullptr, AXLB_EINVAL, "Nr >= 2, Nz >= 1 and Nr*Nz < 2^31 required");
+    if (geo->kind != AXLB_ANNULUS && geo->kind != AXLB_CYLINDER)
+        return fail(nullptr, AXLB_EINVAL, "unknown geometry kind");
+    if (geo->kind == AXLB_ANNULUS && !(geo->r_inner > 0.0 && std::isfinite(geo->r_inner)))
+        return fail(nullptr, AXLB_EINVAL, "annulus needs r_inner > 0");
+    if (!(nu > 0.0 && std::isfinite(nu)) || !(alpha > 0.0 && std::isfinite(alpha)))
+        return fail(nullptr, AXLB_EINVAL, "nu > 0 and alpha > 0 required (relaxation time > 1/2)");
+    if (Pr != 0.0 && !(std::fabs(Pr - nu / alpha) <= 1e-9 * std::fabs(Pr)))
+        return fail(nullptr, AXLB_EINVAL, "Pr differs from nu/alpha");
+    if (!(Ra >= 0.0 && std::isfinite(Ra))) return fail(nullptr, AXLB_EINVAL, "Ra must be >= 0");
+    axlb_relax R = {1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
+    if (w) R = *w;
+    for (double x : {R.omega3, R.omega6, R.omega7, R.omega8, R.omega_psi3, R.omega_psi4,
+                     R.omega_phi3, R.omega_phi4})
+        if (!rate_ok(x)) return fail(nullptr, AXLB_EINVAL, "relaxation rates must lie in (0, 2)");
+    axlb_options O;
+    std::memset(&O, 0, sizeof(O));
+    O.storage = AXLB_F32;
+    O.layout = AXLB_LAYOUT_AA;
+    O.T_ref = 0.5;
+    O.device = -1;
+    if (opt) O = *opt;
+    if (O.storage < 0 || O.storage > 2) return fail(nullptr, AXLB_EINVAL, "unknown storage");
+    if (O.layout < 0 || O.layout > 1) return fail(nullptr, AXLB_EINVAL, "unknown layout");
+    if (!std::isfinite(O.T_ref)) return fail(nullptr, AXLB_EINVAL, "T_ref must be finite");
+
+    axlb_lattice *L = new (std::nothrow) axlb_lattice();
+    if (!L) return fail(nullptr, AXLB_ENOMEM, "host allocation failed");
+    L->Nr = Nr;
+    L->Nz = Nz;
+    L->cylinder = geo->kind == AXLB_CYLINDER;
+    L->r_inner = L->cylinder ? 0.0 : geo->r_inner;
+    L->nu = nu;
+    L->alpha = alpha;
+    L->Ra = Ra;
+    L->Omega = Omega;
+    L->gbeta = Ra * nu * alpha / ((double)Nr * Nr * Nr);
+    L->T0 = 0.5;
+    L->relax = R;
+    L->storage = O.storage;
+    L->layout = O.layout;
+    L->T_ref = O.T_ref;
+    for (int f = 0; f < 4; ++f) {
+        L->kind[f][0] = AXLB_NOSLIP;
+        L->kind[f][1] = AXLB_NOSLIP;
+        L->kind[f][2] = AXLB_ADIABATIC;
+        for (int d = 0; d < 3; ++d) L->val[f][d] = 0.0;
+    }
+    if (L->cylinder)
+        for (int d = 0; d < 3; ++d) L->kind[AXLB_R_IN][d] = AXLB_MIRROR;
+
+    auto bad = [&](int code, const std::string &m) {
+        g_create_error = m;
+        axlb_destroy(L);
+        return code;
+    };
+    int dev = O.device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return bad(AXLB_EDEVICE, "hipGetDevice failed");
+    L->device = dev;
+    if (hipSetDevice(dev) != hipSuccess) return bad(AXLB_EDEVICE, "hipSetDevice failed");
+    L->lay = layout_for(Nr, Nz, L->storage, L->layout);
+    if (O.device_buf) {
+        if (O.device_bytes < L->lay.total || ((uintptr_t)O.device_buf & 255))
+            return bad(AXLB_EINVAL, "device_buf too small or not 256-byte aligned");
+        L->base = (char *)O.device_buf;
+        L->own_mem = false;
+    } else {
+        if (hipMalloc((void **)&L->base, L->lay.total) != hipSuccess) {
+            L->base = nullptr;
+            return bad(AXLB_ENOMEM, "hipMalloc of the lattice state failed");
+        }
+        L->own_mem = true;
+    }
+    char *p = L->base;
+    L->pop[0] = p;
+    p += L->lay.pop_bytes;
+    if (L->layout == AXLB_LAYOUT_AB) {
+        L->pop[1] = p;
+        p += L->lay.pop_bytes;
+    } else {
+        L->pop[1] = L->pop[0];
+    }
+    L->lag[0] = (float *)p;
+    p += L->lay.lag_bytes;
+    L->lag[1] = (float *)p;
+    p += L->lay.lag_bytes;
+    L->fld = (double *)p;
+    p += L->lay.fld_bytes;
+    L->snap = (double *)p;
+    p += L->lay.snap_bytes;
+    L->red = (double *)p;
+    if (O.stream) {
+        L->stream = (hipStream_t)O.stream;
+        L->own_stream = false;
+    } else {
+        if (hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
+            return bad(AXLB_EDEVICE, "hipStreamCreate failed");
+        L->own_stream = true;
+    }
+    // zero everything once so that padding never holds garbage
+    if (hipMemsetAsync(L->base, 0, L->lay.total, L->stream) != hipSuccess)
+        return bad(AXLB_EDEVICE, "hipMemsetAsync failed");
+    L->P = make_params(L);
+    int rc = axlb_set_fields(L, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (rc != AXLB_OK) return bad(rc, L->err);
+    *out = L;
+    return AXLB_OK;
+}
+
+int axlb_set_bc(axlb_lattice *L, int face, int field, int kind, double value) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (L->started) return fail(L, AXLB_ESTATE, "boundary rules are fixed once stepping started");
+    if (face < 0 || face > 3 || field < 0 || field > 2 || kind < 0 || kind > 5)
+        return fail(L, AXLB_EINVAL, "face, field or kind out of range");
+    if (L->cylinder && face == AXLB_R_IN && kind != AXLB_MIRROR)
+        return fail(L, AXLB_EINVAL, "the inner face of a cylinder is the axis");
+    if (kind == AXLB_MIRROR && !(L->cylinder && face == AXLB_R_IN))
+        return fail(L, AXLB_EINVAL, "MIRROR is only the axis of a cylinder");
+    if (kind == AXLB_PERIODIC && face != AXLB_Z_LO && face != AXLB_Z_HI)
+        return fail(L, AXLB_EINVAL, "PERIODIC is only for z faces");
+    if (field == AXLB_FLOW && (kind == AXLB_DIRICHLET || kind == AXLB_OMEGA_R || kind == AXLB_ADIABATIC))
+        return fail(L, AXLB_EINVAL, "FLOW walls are NOSLIP");
+    if (field == AXLB_THERMAL && (kind == AXLB_NOSLIP || kind == AXLB_OMEGA_R))
+        return fail(L, AXLB_EINVAL, "THERMAL walls are DIRICHLET or ADIABATIC");
+    if (kind == AXLB_DIRICHLET && !std::isfinite(value))
+        return fail(L, AXLB_EINVAL, "DIRICHLET value must be finite");
+    if (kind == AXLB_OMEGA_R && std::isinf(value))
+        return fail(L, AXLB_EINVAL, "OMEGA_R value must be finite or NaN");
+    L->kind[face][field] = kind;
+    L->val[face][field] = value;
+    L->P = make_params(L);
+    return AXLB_OK;
+}
+
+int axlb_set_body_force(axlb_lattice *L, double g_axial, double T0) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (L->started) return fail(L, AXLB_ESTATE, "body force is fixed once stepping started");
+    if (!std::isfinite(g_axial) || !std::isfinite(T0)) return fail(L, AXLB_EINVAL, "non-finite force");
+    L->g_axial = g_axial;
+    L->T0 = T0;
+    L->P = make_params(L);
+    return AXLB_OK;
+}
+
+int axlb_set_fields(axlb_lattice *L, const double *rho, const double *ur, const double *uz,
+                    const double *uth, const double *T) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = (size_t)L->Nr * L->Nz;
+    std::vector<double> h(5 * N);
+    for (size_t k = 0; k < N; ++k) {
+        h[k] = rho ? rho[k] : 1.0;
+        h[N + k] = ur ? ur[k] : 0.0;
+        h[2 * N + k] = uz ? uz[k] : 0.0;
+        h[3 * N + k] = uth ? uth[k] : 0.0;
+        h[4 * N + k] = T ? T[k] : L->T_ref;
+        for (int c = 0; c < 5; ++c)
+            if (!std::isfinite(h[c * N + k])) return fail(L, AXLB_EINVAL, "non-finite initial field");
+        if (!(h[k] > 0.0)) return fail(L, AXLB_EINVAL, "initial density must be positive");
+    }
+    HIP_TRY(L, hipMemcpyAsync(L->fld, h.data(), 5 * N * sizeof(double), hipMemcpyHostToDevice,
+                              L->stream));
+    hipError_t e = launch_init(L->P, L->storage, L->layout == AXLB_LAYOUT_AA, L->pop[0], L->fld,
+                               L->lag[0], L->stream);
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("init launch: ") + hipGetErrorString(e));
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    L->steps = 0;
+    L->has_snap = false;
+    return AXLB_OK;
+}
+
+int axlb_step(axlb_lattice *L, long n) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (n < 0) return fail(L, AXLB_EINVAL, "negative step count");
+    if (n == 0) return AXLB_OK;
+    int rc = set_device(L);
+    if (rc) return rc;
+    if (!L->started) {
+        rc = check_bcs(L);
+        if (rc) return rc;
+        L->P = make_params(L);
+        L->started = true;
+    }
+    while (n > 0) {
+        if (n >= BUNDLE && L->use_graphs) {
+            const int k = (int)(L->steps & 1);
+            rc = ensure_graph(L, k);
+            if (rc) return rc;
+            HIP_TRY(L, hipGraphLaunch(L->graph_exec[k], L->stream));
+            L->steps += BUNDLE;
+            n -= BUNDLE;
+        } else {
+            rc = launch_one(L, L->steps);
+            if (rc) return rc;
+            L->steps += 1;
+            n -= 1;
+        }
+    }
+    return AXLB_OK;
+}
+
+long axlb_steps_done(const axlb_lattice *L) { return L ? L->steps : -1; }
+
+int axlb_sync(axlb_lattice *L) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    return AXLB_OK;
+}
+
+int axlb_get_moments(axlb_lattice *L, double *rho, double *ur, double *uz, double *uth,
+                     double *T) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    int rc = set_device(L);
+    if (rc) return rc;
+    rc = compute_fields(L);
+    if (rc) return rc;
+    const size_t N = (size_t)L->Nr * L->Nz;
+    double *dst[5] = {rho, ur, uz, uth, T};
+    for (int c = 0; c < 5; ++c)
+        if (dst[c])
+            HIP_TRY(L, hipMemcpyAsync(dst[c], L->fld + c * N, N * sizeof(double),
+                                      hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    return AXLB_OK;
+}
+
+int axlb_nusselt(axlb_lattice *L, double *nu_a, double *nu_b, double *mean) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    const int fa = L->cylinder ? AXLB_Z_LO : AXLB_R_IN, fb = L->cylinder ? AXLB_Z_HI : AXLB_R_OUT;
+    if (L->kind[fa][2] != AXLB_DIRICHLET || L->kind[fb][2] != AXLB_DIRICHLET)
+        return fail(L, AXLB_ESTATE, "Nusselt numbers need imposed T on both heat-transfer walls");
+    const double Ta = L->val[fa][2], Tb = L->val[fb][2];
+    const double dT = L->cylinder ? Tb - Ta : Ta - Tb;
+    if (dT == 0.0) return fail(L, AXLB_ESTATE, "the two wall temperatures are equal");
+    if ((L->cylinder && L->Nz < 2) || L->Nr < 2)
+        return fail(L, AXLB_ESTATE, "too few nodes for the wall gradient");
+    int rc = set_device(L);
+    if (rc) return rc;
+    rc = compute_fields(L);
+    if (rc) return rc;
+    const size_t N = (size_t)L->Nr * L->Nz;
+    double *out = L->red + RED_BLOCKS * 9;
+    hipError_t e = launch_nusselt(L->fld + 4 * N, L->Nr, L->Nz, L->cylinder, L->r_inner, Ta, Tb,
+                                  out, L->stream);
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("nusselt launch: ") + hipGetErrorString(e));
+    double s[2];
+    HIP_TRY(L, hipMemcpyAsync(s, out, sizeof(s), hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    double a, b;
+    if (!L->cylinder) {
+        // Section 3.2: Nu = -R/(H dT) int d_y T dx over the wall
+        const double H = L->Nz, Ri = L->r_inner, Ro = L->r_inner + L->Nr;
+        a = -Ri / (H * dT) * s[0];
+        b = -Ro / (H * dT) * s[1];
+    } else {
+        const double H = L->Nz, R = L->Nr;
+        a = H / dT * 2.0 / (R * R) * s[0];
+        b = H / dT * 2.0 / (R * R) * s[1];
+    }
+    if (nu_a) *nu_a = a;
+    if (nu_b) *nu_b = b;
+    if (mean) *mean = 0.5 * (a + b);
+    return AXLB_OK;
+}
+
+int axlb_residual(axlb_lattice *L, double *r) {
+    if (!L || !r) return fail(L, AXLB_EINVAL, "NULL argument");
+    int rc = set_device(L);
+    if (rc) return rc;
+    rc = compute_fields(L);
+    if (rc) return rc;
+    const size_t N = (size_t)L->Nr * L->Nz;
+    double *out = L->red + RED_BLOCKS * 9;
+    hipError_t e = launch_residual(L->fld, L->snap, (long long)N, L->red, RED_BLOCKS, out, L->stream);
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("residual launch: ") + hipGetErrorString(e));
+    double s[9];
+    HIP_TRY(L, hipMemcpyAsync(s, out, sizeof(s), hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(L, hipMemcpyAsync(L->snap, L->fld + N, 4 * N * sizeof(double),
+                              hipMemcpyDeviceToDevice, L->stream));
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    const bool had = L->has_snap;
+    const long K = L->steps - L->snap_step;
+    L->has_snap = true;
+    L->snap_step = L->steps;
+    if (s[8] != 0.0) {
+        *r = NAN;
+        return fail(L, AXLB_EUNSTABLE, "non-finite value in the fields");
+    }
+    if (!had || K <= 0) {
+        *r = INFINITY;
+        return AXLB_OK;
+    }
+    double m = 0.0;
+    for (int c = 0; c < 4; ++c)
+        if (s[2 * c + 1] > 0.0) m = std::fmax(m, std::sqrt(s[2 * c]) / ((double)K * std::sqrt(s[2 * c + 1])));
+    *r = m;
+    return AXLB_OK;
+}
+
+// Checkpoint image: header, then the population buffer the next step reads,
+// then the lagged fields it reads.
+struct Header {
+    uint64_t magic;
+    int32_t Nr, Nz, storage, layout;
+    int64_t steps;
+    uint64_t pop_bytes, lag_bytes;
+};
+static const uint64_t MAGIC = 0x31424c584131ULL;  // "1AXLB1"
+
+int axlb_state_size(const axlb_lattice *L, size_t *bytes) {
+    if (!L || !bytes) return fail(nullptr, AXLB_EINVAL, "NULL argument");
+    *bytes = sizeof(Header) + L->lay.pop_bytes + L->lay.lag_bytes;
+    return AXLB_OK;
+}
+
+int axlb_save(axlb_lattice *L, void *host, size_t bytes) {
+    if (!L || !host) return fail(L, AXLB_EINVAL, "NULL argument");
+    size_t need;
+    axlb_state_size(L, &need);
+    if (bytes < need) return fail(L, AXLB_EINVAL, "buffer too small");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const int par = (int)(L->steps & 1);
+    Header h = {MAGIC, L->Nr, L->Nz, L->storage, L->layout, L->steps, L->lay.pop_bytes, L->lay.lag_bytes};
+    char *p = (char *)host;
+    std::memcpy(p, &h, sizeof(h));
+    void *pop = L->layout == AXLB_LAYOUT_AA ? L->pop[0] : L->pop[par];
+    HIP_TRY(L, hipMemcpyAsync(p + sizeof(h), pop, L->lay.pop_bytes, hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(L, hipMemcpyAsync(p + sizeof(h) + L->lay.pop_bytes, L->lag[par], L->lay.lag_bytes,
+                              hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    return AXLB_OK;
+}
+
+int axlb_load(axlb_lattice *L, const void *host, size_t bytes) {
+    if (!L || !host) return fail(L, AXLB_EINVAL, "NULL argument");
+    size_t need;
+    axlb_state_size(L, &need);
+    Header h;
+    if (bytes < need) return fail(L, AXLB_EINVAL, "image too small");
+    std::memcpy(&h, host, sizeof(h));
+    if (h.magic != MAGIC || h.Nr != L->Nr || h.Nz != L->Nz || h.storage != L->storage ||
+        h.layout != L->layout || h.pop_bytes != L->lay.pop_bytes || h.lag_bytes != L->lay.lag_bytes ||
+        h.steps < 0)
+        return fail(L, AXLB_EINVAL, "image does not match this lattice");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const int par = (int)(h.steps & 1);
+    const char *p = (const char *)host;
+    void *pop = L->layout == AXLB_LAYOUT_AA ? L->pop[0] : L->pop[par];
+    HIP_TRY(L, hipMemcpyAsync(pop, p + sizeof(h), L->lay.pop_bytes, hipMemcpyHostToDevice, L->stream));
+    HIP_TRY(L, hipMemcpyAsync(L->lag[par], p + sizeof(h) + L->lay.pop_bytes, L->lay.lag_bytes,
+                              hipMemcpyHostToDevice, L->stream));
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    L->steps = h.steps;
+    L->has_snap = false;
+    return AXLB_OK;
+}
+
+void axlb_destroy(axlb_lattice *L) {
+    if (!L) return;
+    (void)hipSetDevice(L->device);
+    if (L->stream) (void)hipStreamSynchronize(L->stream);
+    for (int k = 0; k < 2; ++k)
+        if (L->graph_exec[k]) (void)hipGraphExecDestroy(L->graph_exec[k]);
+    if (L->own_mem && L->base) (void)hipFree(L->base);
+    if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
+    delete L;
+}
+
+const char *axlb_last_error(const axlb_lattice *L) {
+    return L ? L->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

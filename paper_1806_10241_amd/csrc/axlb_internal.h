@@ -1,0 +1,53 @@
+// Host-side lattice object of the HIP library.  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/axlb.h"
+#include "axlb_device.h"
+
+namespace axlb {
+
+constexpr long BUNDLE = 100;      // steps per captured HIP graph
+constexpr int RED_BLOCKS = 256;   // partial sums of the FP64 reductions
+
+struct Layout {
+    int pitch;                 // row pitch in elements (multiple of 64)
+    long long plane;           // elements per plane
+    size_t pop_bytes, lag_bytes, fld_bytes, snap_bytes, red_bytes, total;
+};
+
+size_t storage_size(int storage);
+Layout layout_for(int Nr, int Nz, int storage, int layout);
+
+}  // namespace axlb
+
+struct axlb_lattice {
+    int Nr = 0, Nz = 0, cylinder = 0;
+    double r_inner = 0, nu = 0, alpha = 0, Ra = 0, Omega = 0, gbeta = 0, g_axial = 0, T0 = 0.5;
+    double T_ref = 0.5;
+    axlb_relax relax{};
+    int storage = 0, layout = 0;
+    int kind[4][3]{};
+    double val[4][3]{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false, own_mem = false;
+    axlb::Layout lay{};
+    char *base = nullptr;
+    void *pop[2] = {nullptr, nullptr};
+    float *lag[2] = {nullptr, nullptr};
+    double *fld = nullptr, *snap = nullptr, *red = nullptr;
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    bool use_graphs = true;
+    bool started = false, has_snap = false;
+    long steps = 0, snap_step = 0;
+    axlb::KParams P{};
+    std::string err;
+};
+
+namespace axlb {
+KParams make_params(const axlb_lattice *L);
+}

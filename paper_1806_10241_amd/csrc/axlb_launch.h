@@ -1,0 +1,25 @@
+// Host launchers of the step, field, initialisation and reduction kernels.
+// Internal to the HIP library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "axlb_device.h"
+
+namespace axlb {
+
+enum { STORE_F32 = 0, STORE_F16 = 1, STORE_BF16 = 2 };
+
+// mode: 0 = AB pull (src -> dst), 1 = AA odd phase, 2 = AA even phase (src == dst).
+hipError_t launch_step(const KParams &P, int storage, int mode, void *src, void *dst,
+                       const float *Mprev, float *Mnext, hipStream_t st);
+hipError_t launch_fields(const KParams &P, int storage, int mode, const void *src,
+                         const float *Mprev, double *out, hipStream_t st);
+hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
+                       float *M, hipStream_t st);
+hipError_t launch_residual(const double *fld, const double *snap, long long N, double *part,
+                           int nblocks, double *out9, hipStream_t st);
+hipError_t launch_nusselt(const double *T, int Nr, int Nz, int cylinder, double r0, double Ta,
+                          double Tb, double *out2, hipStream_t st);
+
+}  // namespace axlb

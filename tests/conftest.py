@@ -18,3 +18,20 @@ def orc():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """The HIP library on cuda:0; tests marked gpu skip only where no GPU
+    exists at all (the CPU suite deselects them anyway)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU on this host")
+    from paper_1806_10241_amd import axlb
+    axlb.load()
+    return torch
+
+
+def say(*a):
+    """Progress line that names the GPU case about to run."""
+    print(*a, flush=True)

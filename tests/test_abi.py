@@ -1,0 +1,51 @@
+"""The C-ABI library loads on a host without a GPU and exports every
+function that include/axlb.h declares; argument validation that needs no
+device works (no compute calls here)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "axlb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(axlb_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_bound_functions():
+    from paper_1806_10241_amd import axlb
+    assert header_functions() == sorted(axlb.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1806_10241_amd import axlb
+    lib = axlb.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_state_bytes_and_argument_checks():
+    from paper_1806_10241_amd import axlb
+    n32 = axlb.state_bytes(1024, 2048, "f32", "aa")
+    n16 = axlb.state_bytes(1024, 2048, "f16", "aa")
+    nab = axlb.state_bytes(1024, 2048, "f32", "ab")
+    pop32 = 19 * 1024 * 2048 * 4
+    assert n32 - n16 == pop32 // 2
+    assert nab - n32 == pop32
+    with pytest.raises(axlb.AxlbError):
+        axlb.state_bytes(1, 10)
+    lib = axlb.load()
+    import ctypes as C
+    out = C.c_void_p()
+    geo = axlb.Geometry(axlb.ANNULUS, 10.0)
+    # nu <= 0 (relaxation time <= 1/2) is rejected before any device call
+    rc = lib.axlb_lattice_create(32, 8, C.byref(geo), 0.0, 0.1, 0.0, 0.0, 0.0, None, None,
+                                 C.byref(out))
+    assert rc == axlb.EINVAL and not out.value
+    assert b"nu" in lib.axlb_last_error(None)
+    rc = lib.axlb_lattice_create(32, 8, C.byref(geo), 0.1, 0.1, 0.7, 0.0, 0.0, None, None,
+                                 C.byref(out))
+    assert rc == axlb.EINVAL  # Pr != nu/alpha
