@@ -13,6 +13,8 @@ from __future__ import annotations
 
 import argparse
 import json
+
+import numpy as np
 import os
 import sys
 import time
@@ -40,6 +42,109 @@ def cpu_baseline(case, steps: int):
                       % (steps, case["Nr"], case["Nz"], dt)}
 
 
+def bench_batched(n, steps, warmup, baseline_steps):
+    """256-way batch of uneven annulus-convection instances (seeded): fused
+    launches with 100-step graph bundles and an autotuned schedule, against
+    the same instances stepped by one launch per instance per step."""
+    from paper_1806_10241_amd import axlb
+    from paper_1806_10241_amd import inputs as I
+
+    cases = I.batched_annuli(n=n, seed=4)
+    lats = [axlb.Lattice(c) for c in cases]
+    nodes = sum(c["Nr"] * c["Nz"] for c in cases)
+    b = axlb.Batch(lats)
+    tile, blocks, _ = b.autotune(steps_per_trial=8)
+    b.step(warmup)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    dt = time.perf_counter() - t0
+    finite = all(np.isfinite(lat.residual()) for lat in lats[:4])
+    b.close()
+    axlb.step_each(lats, 2)
+    for lat in lats:
+        lat.sync()
+    t1 = time.perf_counter()
+    axlb.step_each(lats, baseline_steps)
+    for lat in lats:
+        lat.sync()
+    dt_loop = time.perf_counter() - t1
+    mlups = nodes * steps / dt / 1e6
+    mlups_loop = nodes * baseline_steps / dt_loop / 1e6
+    for lat in lats:
+        lat.close()
+    return {"instances": n, "nodes": nodes, "steps": steps, "mlups": round(mlups, 1),
+            "solves_per_s": round(n / (dt * 1e4 / steps), 3),
+            "solve": "1e4 steps of one instance",
+            "schedule": {"tile": "%dx%d" % axlb.tile_shape(tile), "blocks": blocks},
+            "loop_of_single_launches": {"steps": baseline_steps, "mlups": round(mlups_loop, 1)},
+            "speedup_vs_loop": round(mlups / mlups_loop, 2), "finite": bool(finite)}
+
+
+def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2):
+    """Poisson arrivals of mixed solve requests (seeded trace) served by the
+    continuous-batching pool, against serving the same trace one request at
+    a time with plain single-lattice runs.  Latency = arrival to result."""
+    from paper_1806_10241_amd import axlb
+    from paper_1806_10241_amd import inputs as I
+
+    trace = I.serving_trace(n=n, rate=rate, seed=5, max_nr_log2=max_nr_log2,
+                            max_nz_log2=max_nz_log2)
+    pool = axlb.Pool(budget_bytes=int(budget_gib * (1 << 30)))
+    arrival, done, steps_of = {}, {}, {}
+    pending = list(trace)
+    t0 = time.perf_counter()
+    while pending or len(done) < len(arrival):
+        now = time.perf_counter() - t0
+        while pending and pending[0][0] <= now:
+            at, case, st = pending.pop(0)
+            rid = pool.submit(case, st, tol=tol, max_steps=max_steps)
+            arrival[rid] = at
+        if len(done) < len(arrival):
+            pool.tick()
+            now = time.perf_counter() - t0
+            for rid in arrival:
+                if rid not in done:
+                    state, steps, _ = pool.status(rid)
+                    if state in (axlb.REQ_DONE, axlb.REQ_FAILED):
+                        done[rid] = now
+                        steps_of[rid] = steps
+        elif pending:
+            time.sleep(max(0.0, pending[0][0] - (time.perf_counter() - t0)))
+    makespan = time.perf_counter() - t0
+    _, node_updates = pool.usage()
+    lat_s = np.array([done[r] - arrival[r] for r in arrival])
+    pool.close()
+    # one request at a time: each case alone, same stop rule, FIFO queue
+    finish = 0.0
+    lat1 = []
+    for at, case, st in trace:
+        lat = axlb.Lattice(case, storage=st)
+        t1 = time.perf_counter()
+        lat.residual()
+        while lat.steps < max_steps:
+            lat.step(100)
+            if lat.residual() < tol:
+                break
+        service = time.perf_counter() - t1
+        lat.close()
+        finish = max(finish, at) + service
+        lat1.append(finish - at)
+    lat1 = np.array(lat1)
+    makespan1 = finish
+    return {"requests": n, "rate_per_s": rate, "tol": tol, "max_steps": max_steps,
+            "budget_gib": budget_gib,
+            "grid": "Nr 64..%d x Nz 64..%d" % (2 ** max_nr_log2, 2 ** max_nz_log2),
+            "p50_s": round(float(np.percentile(lat_s, 50)), 4),
+            "p99_s": round(float(np.percentile(lat_s, 99)), 4),
+            "solves_per_s": round(n / makespan, 3),
+            "aggregate_mlups": round(node_updates / makespan / 1e6, 1),
+            "one_at_a_time": {"p50_s": round(float(np.percentile(lat1, 50)), 4),
+                              "p99_s": round(float(np.percentile(lat1, 99)), 4),
+                              "solves_per_s": round(n / makespan1, 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,7 +155,20 @@ def main():
     ap.add_argument("--Nr", type=int, default=1024)
     ap.add_argument("--Nz", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="step-kernel tile shape; -1: autotune on the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-n", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=10000)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--serve-n", type=int, default=48)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-tol", type=float, default=1e-7)
+    ap.add_argument("--serve-max-steps", type=int, default=20000)
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-max-nr-log2", type=float, default=8.0)
+    ap.add_argument("--serve-max-nz-log2", type=float, default=9.0)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--single-launches", action="store_true",
                     help="one kernel launch per step instead of 100-step graphs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -84,6 +202,14 @@ def main():
     lat = axlb.Lattice(case, storage=args.storage, layout=args.layout, stream=stream)
     print("bench: %dx%d %s %s, warmup %d" % (args.Nr, args.Nz, args.storage, args.layout,
                                              args.warmup), file=sys.stderr, flush=True)
+    if args.tile >= 0:
+        lat.set_tile(args.tile)
+        tune = None
+    else:
+        best, ms = lat.autotune(steps_per_trial=40)
+        tune = {"%dx%d" % axlb.tile_shape(t): round(m * 1e3, 2) for t, m in enumerate(ms)}
+        print("bench: autotune us/step per tile %s" % tune, file=sys.stderr, flush=True)
+    tile_id, tile_rz = lat.tile()
     lat.step(args.warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -125,13 +251,22 @@ def main():
         "config": {"workload": "rotating-lid cylinder with buoyancy, Re=1000, Ri=0.5, Pr=1",
                    "Nr": args.Nr, "Nz": args.Nz, "storage": args.storage,
                    "layout": args.layout,
-                   "graph_bundle": 0 if args.single_launches else 100},
+                   "graph_bundle": 0 if args.single_launches else 100,
+                   "tile": "%dx%d" % tile_rz, "autotune_us_per_step": tune},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None},
         "finite": bool(r == r),
     }
     lat.close()
+    if not args.no_batch:
+        print("bench: batched, %d instances" % args.batch_n, file=sys.stderr, flush=True)
+        out["batched"] = bench_batched(args.batch_n, args.batch_steps, 200, 100)
+    if not args.no_serve:
+        print("bench: served, %d requests" % args.serve_n, file=sys.stderr, flush=True)
+        out["served"] = bench_served(args.serve_n, args.serve_rate, args.serve_tol,
+                                     args.serve_max_steps, args.serve_budget_gib,
+                                     args.serve_max_nr_log2, args.serve_max_nz_log2)
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

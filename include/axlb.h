@@ -163,11 +163,13 @@ int axlb_get_moments(axlb_lattice *lat, double *rho, double *ur, double *uz, dou
  * mean = (a + b)/2.  Synchronous. */
 int axlb_nusselt(axlb_lattice *lat, double *nu_a, double *nu_b, double *mean);
 
-/* Convergence residual, FP64 on the device: the largest over u_z, u_r,
- * u_theta, T of ||q_now - q_then||_2 / (K ||q_now||_2), q_then being the
- * fields at the previous call and K the steps in between (fields with zero
- * norm are skipped).  The first call only records the fields and returns
- * +inf.  AXLB_EUNSTABLE if a non-finite value is found.  Synchronous. */
+/* Convergence residual, FP64 on the device: the largest of
+ * ||c_now - c_then||_2 / (K ||speed_now||_2) over the velocity components
+ * c = u_r, u_z, u_theta (speed = |u|) and ||T_now - T_then||_2 /
+ * (K ||T_now||_2), "then" being the fields at the previous call and K the
+ * steps in between (terms with zero norm are skipped).  The first call only
+ * records the fields and returns +inf.  AXLB_EUNSTABLE if a non-finite value
+ * is found.  Synchronous. */
 int axlb_residual(axlb_lattice *lat, double *r);
 
 /* Checkpoint: the whole state (populations, lagged fields, phase, step
@@ -176,7 +178,105 @@ int axlb_state_size(const axlb_lattice *lat, size_t *bytes);
 int axlb_save(axlb_lattice *lat, void *host, size_t bytes);
 int axlb_load(axlb_lattice *lat, const void *host, size_t bytes);
 
+/* Step-kernel tile shapes: AXLB_NTILES workgroup shapes of tile_r x tile_z
+ * nodes.  axlb_set_tile selects one for a lattice (results do not depend on
+ * it); axlb_autotune times every shape for steps_per_trial steps on the
+ * lattice itself, restores the state it found, selects the fastest, and
+ * returns the per-step times in ms_per_step[AXLB_NTILES] (may be NULL). */
+#define AXLB_NTILES 8
+int axlb_tile_shape(int tile, int *tile_r, int *tile_z);
+int axlb_set_tile(axlb_lattice *lat, int tile);
+int axlb_get_tile(const axlb_lattice *lat, int *tile, int *tile_r, int *tile_z);
+int axlb_autotune(axlb_lattice *lat, int steps_per_trial, double *ms_per_step, int *best);
+
 void axlb_destroy(axlb_lattice *lat);
+
+/* ---- batches of independent lattices (uneven sizes) ----
+ * A batch advances all its member lattices together: every step of every
+ * member is one fused launch over a work-list of (member, tile) entries, and
+ * 100-step bundles are captured as HIP graphs.  Members must share device
+ * and storage, use the AA layout and belong to no other batch; their
+ * boundary rules are locked.  While batched, a member runs on the batch's
+ * stream: axlb_get_moments, axlb_nusselt, axlb_residual and axlb_save work
+ * on it as usual, whereas axlb_step, axlb_set_fields, axlb_load,
+ * axlb_set_tile, axlb_autotune and axlb_destroy refuse (AXLB_ESTATE).  A
+ * member's results are bit-identical to stepping it alone.  The batch does
+ * not own its members: destroy the batch first, then the lattices. */
+typedef struct axlb_batch axlb_batch;
+#define AXLB_NSCHEDULES 4 /* launch schedules the batch autotuner tries */
+
+int axlb_batch_create(axlb_lattice *const *lats, int n, axlb_batch **out);
+int axlb_batch_size(const axlb_batch *b, int *members, long long *nodes);
+/* Enqueues n steps of every member (asynchronous on the batch stream). */
+int axlb_batch_step(axlb_batch *b, long n);
+int axlb_batch_sync(axlb_batch *b);
+/* Tile shape (as axlb_tile_shape) and schedule: blocks = 0 launches one
+ * workgroup per work-list entry, blocks > 0 that many persistent workgroups
+ * that loop over the entries. */
+int axlb_batch_set_schedule(axlb_batch *b, int tile, int blocks);
+int axlb_batch_get_schedule(const axlb_batch *b, int *tile, int *blocks);
+/* Times every tile shape with each of the AXLB_NSCHEDULES schedules (one
+ * workgroup per entry, 4, 8 and 16 persistent workgroups per compute unit)
+ * for steps_per_trial steps, restores the members' state, keeps the
+ * fastest.  ms_per_step[AXLB_NTILES * AXLB_NSCHEDULES] may be NULL. */
+int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
+                        int *best_tile, int *best_blocks);
+void axlb_batch_destroy(axlb_batch *b);
+const char *axlb_batch_last_error(const axlb_batch *b);
+
+/* The unbatched form, for comparison: advances each of n lattices by
+ * `steps` steps with one kernel launch per lattice per step. */
+int axlb_step_each(axlb_lattice *const *lats, int n, long steps);
+
+/* ---- continuous-batching request pool ----
+ * Solve requests (any size, parameters and storage) wait in a first-come
+ * first-served queue and are admitted while their state fits a fixed
+ * device-memory budget (and at most max_members run at once).  Admitted
+ * requests stay resident and advance together: each axlb_pool_tick runs one
+ * 100-step bundle of every resident request as fused batched launches (one
+ * batch per storage type, overlapping on the device), then retires every
+ * request whose residual (axlb_residual, checked once per bundle) is below
+ * its tol or whose step count reached max_steps.  Requests submitted
+ * between ticks join at the next tick.  A request's result is bit-identical
+ * to running the same case alone for the same number of steps. */
+typedef struct axlb_pool axlb_pool;
+#define AXLB_REQ_QUEUED 0
+#define AXLB_REQ_RUNNING 1
+#define AXLB_REQ_DONE 2
+#define AXLB_REQ_FAILED 3
+
+typedef struct {
+    int Nr, Nz;
+    axlb_geometry geo;
+    double nu, alpha, Pr, Ra, Omega; /* as axlb_lattice_create           */
+    double g_axial, T0;              /* as axlb_set_body_force           */
+    int bc_kind[4][3];               /* [face][field], as axlb_set_bc    */
+    double bc_value[4][3];
+    int storage;                     /* AXLB_F32 | AXLB_F16 | AXLB_BF16  */
+    double T_ref;
+    const double *init[5];           /* optional host fields rho, u_r, u_z,
+                                        u_theta, T ([iz][ir]); copied at
+                                        submission                       */
+    double tol;                      /* retire when the residual < tol   */
+    long max_steps;                  /* ... or at this many steps         */
+} axlb_request;
+
+int axlb_pool_create(size_t budget_bytes, int device, int max_members, axlb_pool **out);
+/* Queues a request (copies it); *id identifies it.  AXLB_ENOMEM if its
+ * state alone exceeds the budget. */
+int axlb_pool_submit(axlb_pool *p, const axlb_request *r, long *id);
+/* Admission, one bundle for all resident requests, retirement.
+ * Synchronous; reports how many requests run and wait afterwards. */
+int axlb_pool_tick(axlb_pool *p, int *running, int *queued);
+int axlb_pool_status(const axlb_pool *p, long id, int *state, long *steps, double *residual);
+/* Final fields (host arrays of Nz*Nr, any may be NULL) and wall Nusselt
+ * numbers (NaN when the case has no imposed wall temperatures) of a DONE
+ * request, which is then forgotten; a FAILED request returns its error. */
+int axlb_pool_result(axlb_pool *p, long id, double *rho, double *ur, double *uz, double *uth,
+                     double *T, double *nusselt3);
+int axlb_pool_usage(const axlb_pool *p, size_t *used_bytes, long long *node_updates);
+void axlb_pool_destroy(axlb_pool *p);
+const char *axlb_pool_last_error(const axlb_pool *p);
 /* Message of the last failed call on lat (or of the last failed create when
  * lat is NULL).  Valid until the next call on lat. */
 const char *axlb_last_error(const axlb_lattice *lat);

@@ -33,8 +33,16 @@ EXPORTS = [
     "axlb_state_bytes", "axlb_lattice_create", "axlb_set_bc", "axlb_set_body_force",
     "axlb_set_fields", "axlb_step", "axlb_steps_done", "axlb_sync", "axlb_get_moments",
     "axlb_nusselt", "axlb_residual", "axlb_state_size", "axlb_save", "axlb_load",
-    "axlb_destroy", "axlb_last_error",
+    "axlb_destroy", "axlb_last_error", "axlb_tile_shape", "axlb_set_tile", "axlb_get_tile",
+    "axlb_autotune", "axlb_batch_create", "axlb_batch_size", "axlb_batch_step",
+    "axlb_batch_sync", "axlb_batch_set_schedule", "axlb_batch_get_schedule",
+    "axlb_batch_autotune", "axlb_batch_destroy", "axlb_batch_last_error", "axlb_step_each",
+    "axlb_pool_create", "axlb_pool_submit", "axlb_pool_tick", "axlb_pool_status",
+    "axlb_pool_result", "axlb_pool_usage", "axlb_pool_destroy", "axlb_pool_last_error",
 ]
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+NTILES = 8
+NSCHEDULES = 4
 
 
 class AxlbError(RuntimeError):
@@ -56,6 +64,16 @@ class Options(C.Structure):
     _fields_ = [("storage", C.c_int), ("layout", C.c_int), ("T_ref", C.c_double),
                 ("stream", C.c_void_p), ("device", C.c_int), ("device_buf", C.c_void_p),
                 ("device_bytes", C.c_size_t)]
+
+
+class Request(C.Structure):
+    _fields_ = [("Nr", C.c_int), ("Nz", C.c_int), ("geo", Geometry), ("nu", C.c_double),
+                ("alpha", C.c_double), ("Pr", C.c_double), ("Ra", C.c_double),
+                ("Omega", C.c_double), ("g_axial", C.c_double), ("T0", C.c_double),
+                ("bc_kind", (C.c_int * 3) * 4), ("bc_value", (C.c_double * 3) * 4),
+                ("storage", C.c_int), ("T_ref", C.c_double),
+                ("init", C.POINTER(C.c_double) * 5), ("tol", C.c_double),
+                ("max_steps", C.c_long)]
 
 
 _lib = None
@@ -89,7 +107,31 @@ def load():
         "axlb_save": ([_vp, _vp, C.c_size_t], C.c_int),
         "axlb_load": ([_vp, _vp, C.c_size_t], C.c_int),
         "axlb_destroy": ([_vp], None),
+        "axlb_tile_shape": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "axlb_set_tile": ([_vp, C.c_int], C.c_int),
+        "axlb_get_tile": ([_vp] + [C.POINTER(C.c_int)] * 3, C.c_int),
+        "axlb_autotune": ([_vp, C.c_int, _dp, C.POINTER(C.c_int)], C.c_int),
         "axlb_last_error": ([_vp], C.c_char_p),
+        "axlb_batch_create": ([C.POINTER(_vp), C.c_int, C.POINTER(_vp)], C.c_int),
+        "axlb_batch_size": ([_vp, C.POINTER(C.c_int), C.POINTER(C.c_longlong)], C.c_int),
+        "axlb_batch_step": ([_vp, C.c_long], C.c_int),
+        "axlb_batch_sync": ([_vp], C.c_int),
+        "axlb_batch_set_schedule": ([_vp, C.c_int, C.c_int], C.c_int),
+        "axlb_batch_get_schedule": ([_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "axlb_batch_autotune": ([_vp, C.c_int, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+                                C.c_int),
+        "axlb_batch_destroy": ([_vp], None),
+        "axlb_batch_last_error": ([_vp], C.c_char_p),
+        "axlb_step_each": ([C.POINTER(_vp), C.c_int, C.c_long], C.c_int),
+        "axlb_pool_create": ([C.c_size_t, C.c_int, C.c_int, C.POINTER(_vp)], C.c_int),
+        "axlb_pool_submit": ([_vp, C.POINTER(Request), C.POINTER(C.c_long)], C.c_int),
+        "axlb_pool_tick": ([_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "axlb_pool_status": ([_vp, C.c_long, C.POINTER(C.c_int), C.POINTER(C.c_long), _dp],
+                             C.c_int),
+        "axlb_pool_result": ([_vp, C.c_long] + [_dp] * 6, C.c_int),
+        "axlb_pool_usage": ([_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_longlong)], C.c_int),
+        "axlb_pool_destroy": ([_vp], None),
+        "axlb_pool_last_error": ([_vp], C.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -110,6 +152,15 @@ def state_bytes(Nr, Nz, storage="f32", layout="aa") -> int:
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(_dp)
+
+
+def tile_shape(tile: int):
+    lib = load()
+    r, z = C.c_int(), C.c_int()
+    rc = lib.axlb_tile_shape(int(tile), C.byref(r), C.byref(z))
+    if rc:
+        raise AxlbError(rc, lib.axlb_last_error(None).decode())
+    return r.value, z.value
 
 
 class Lattice:
@@ -223,6 +274,187 @@ class Lattice:
         buf = C.create_string_buffer(image, len(image))
         self._check(self._lib.axlb_load(self._h, buf, len(image)))
 
+    def set_tile(self, tile: int):
+        self._check(self._lib.axlb_set_tile(self._h, int(tile)))
+
+    def tile(self):
+        t, r, z = C.c_int(), C.c_int(), C.c_int()
+        self._check(self._lib.axlb_get_tile(self._h, C.byref(t), C.byref(r), C.byref(z)))
+        return t.value, (r.value, z.value)
+
+    def autotune(self, steps_per_trial: int = 50):
+        """Times every tile shape on this lattice (state restored), keeps the
+        fastest; returns (best, [ms per step per tile])."""
+        ms = np.zeros(NTILES)
+        best = C.c_int()
+        self._check(self._lib.axlb_autotune(self._h, int(steps_per_trial), _ptr(ms), C.byref(best)))
+        return best.value, list(ms)
+
     @property
     def handle(self):
         return self._h
+
+
+def _handles(lattices):
+    arr = (_vp * len(lattices))()
+    for k, lat in enumerate(lattices):
+        arr[k] = lat.handle
+    return arr
+
+
+def step_each(lattices, steps: int):
+    """The unbatched form: one launch per lattice per step."""
+    lib = load()
+    rc = lib.axlb_step_each(_handles(lattices), len(lattices), int(steps))
+    if rc:
+        raise AxlbError(rc, lib.axlb_batch_last_error(None).decode())
+
+
+class Batch:
+    """Fused stepping of several lattices (``axlb_batch_*``).  Keeps the
+    member objects alive; close the batch before the members."""
+
+    def __init__(self, lattices):
+        lib = load()
+        self._lib = lib
+        self.members = list(lattices)
+        self._h = _vp()
+        rc = lib.axlb_batch_create(_handles(self.members), len(self.members), C.byref(self._h))
+        if rc:
+            raise AxlbError(rc, lib.axlb_batch_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc:
+            raise AxlbError(rc, self._lib.axlb_batch_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            self._lib.axlb_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n: int = 1):
+        self._check(self._lib.axlb_batch_step(self._h, int(n)))
+
+    def sync(self):
+        self._check(self._lib.axlb_batch_sync(self._h))
+
+    def size(self):
+        m, nodes = C.c_int(), C.c_longlong()
+        self._check(self._lib.axlb_batch_size(self._h, C.byref(m), C.byref(nodes)))
+        return m.value, nodes.value
+
+    def set_schedule(self, tile: int, blocks: int = 0):
+        self._check(self._lib.axlb_batch_set_schedule(self._h, int(tile), int(blocks)))
+
+    def schedule(self):
+        t, b = C.c_int(), C.c_int()
+        self._check(self._lib.axlb_batch_get_schedule(self._h, C.byref(t), C.byref(b)))
+        return t.value, b.value
+
+    def autotune(self, steps_per_trial: int = 10):
+        """Times every (tile shape, schedule); keeps the fastest.  Returns
+        (tile, blocks, ms[tile][schedule])."""
+        ms = np.zeros(NTILES * NSCHEDULES)
+        t, b = C.c_int(), C.c_int()
+        self._check(self._lib.axlb_batch_autotune(self._h, int(steps_per_trial), _ptr(ms),
+                                                  C.byref(t), C.byref(b)))
+        return t.value, b.value, ms.reshape(NTILES, NSCHEDULES)
+
+
+def make_request(case: dict, storage: str = "f32", tol: float = 1e-7,
+                 max_steps: int = 100000, keep=None) -> Request:
+    """C request for a case dict of ``inputs``; `keep` collects the host
+    arrays that must stay alive until submission."""
+    r = Request()
+    r.Nr, r.Nz = int(case["Nr"]), int(case["Nz"])
+    r.geo = Geometry(CYLINDER if case.get("cylinder") else ANNULUS, float(case.get("r_inner", 0.0)))
+    r.nu, r.alpha = float(case["nu"]), float(case["alpha"])
+    r.Pr, r.Ra = float(case.get("Pr", 0.0)), float(case.get("Ra", 0.0))
+    r.Omega = float(case.get("Omega", float("nan")))
+    r.g_axial, r.T0 = float(case.get("g_axial", 0.0)), float(case.get("T0", 0.5))
+    for face in range(4):
+        for fld in range(3):
+            kind, value = case["bc"].get((face, fld), (NOSLIP if fld < 2 else ADIABATIC, 0.0))
+            r.bc_kind[face][fld] = int(kind)
+            r.bc_value[face][fld] = float(value)
+    r.storage = STORAGE[storage]
+    r.T_ref = float(case.get("T_ref", 0.5))
+    fields = case["fields"]() if case.get("fields") is not None else {}
+    keep = keep if keep is not None else []
+    for c, k in enumerate(("rho", "ur", "uz", "uth", "T")):
+        a = fields.get(k)
+        if a is not None:
+            a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+            keep.append(a)
+            r.init[c] = _ptr(a)
+    r.tol, r.max_steps = float(tol), int(max_steps)
+    return r
+
+
+class Pool:
+    """Continuous-batching request pool (``axlb_pool_*``)."""
+
+    def __init__(self, budget_bytes: int, device: int = 0, max_members: int = 4096):
+        lib = load()
+        self._lib = lib
+        self._h = _vp()
+        rc = lib.axlb_pool_create(int(budget_bytes), int(device), int(max_members),
+                                  C.byref(self._h))
+        if rc:
+            raise AxlbError(rc, lib.axlb_pool_last_error(None).decode())
+        self.shapes = {}
+
+    def _check(self, rc):
+        if rc:
+            raise AxlbError(rc, self._lib.axlb_pool_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            self._lib.axlb_pool_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, case: dict, storage: str = "f32", tol: float = 1e-7,
+               max_steps: int = 100000) -> int:
+        keep = []
+        r = make_request(case, storage, tol, max_steps, keep)
+        rid = C.c_long()
+        self._check(self._lib.axlb_pool_submit(self._h, C.byref(r), C.byref(rid)))
+        self.shapes[rid.value] = (int(case["Nz"]), int(case["Nr"]))
+        return rid.value
+
+    def tick(self):
+        run, q = C.c_int(), C.c_int()
+        self._check(self._lib.axlb_pool_tick(self._h, C.byref(run), C.byref(q)))
+        return run.value, q.value
+
+    def status(self, rid: int):
+        st, steps, res = C.c_int(), C.c_long(), C.c_double()
+        self._check(self._lib.axlb_pool_status(self._h, int(rid), C.byref(st), C.byref(steps),
+                                               C.byref(res)))
+        return st.value, steps.value, res.value
+
+    def result(self, rid: int):
+        Nz, Nr = self.shapes.pop(rid)
+        out = {k: np.empty(Nz * Nr) for k in ("rho", "ur", "uz", "uth", "T")}
+        nu = np.empty(3)
+        self._check(self._lib.axlb_pool_result(self._h, int(rid),
+                                               *[_ptr(out[k]) for k in ("rho", "ur", "uz", "uth", "T")],
+                                               _ptr(nu)))
+        return {k: v.reshape(Nz, Nr) for k, v in out.items()}, tuple(nu)
+
+    def usage(self):
+        used, nodes = C.c_size_t(), C.c_longlong()
+        self._check(self._lib.axlb_pool_usage(self._h, C.byref(used), C.byref(nodes)))
+        return used.value, nodes.value

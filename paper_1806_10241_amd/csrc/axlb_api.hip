@@ -126,10 +126,11 @@ static int launch_one(axlb_lattice *L, long t) {
     float *Mprev = L->lag[par], *Mnext = L->lag[par ^ 1];
     hipError_t e;
     if (L->layout == AXLB_LAYOUT_AA)
-        e = launch_step(P, L->storage, par == 0 ? 1 : 2, L->pop[0], L->pop[0], Mprev, Mnext,
-                        L->stream);
+        e = launch_step(P, L->storage, L->tile, par == 0 ? 1 : 2, L->pop[0], L->pop[0], Mprev,
+                        Mnext, L->stream);
     else
-        e = launch_step(P, L->storage, 0, L->pop[par], L->pop[par ^ 1], Mprev, Mnext, L->stream);
+        e = launch_step(P, L->storage, L->tile, 0, L->pop[par], L->pop[par ^ 1], Mprev, Mnext,
+                        L->stream);
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return AXLB_OK;
 }
@@ -155,6 +156,14 @@ static int ensure_graph(axlb_lattice *L, int k) {
     return AXLB_OK;
 }
 
+static void drop_graphs(axlb_lattice *L) {
+    for (int k = 0; k < 2; ++k)
+        if (L->graph_exec[k]) {
+            (void)hipGraphExecDestroy(L->graph_exec[k]);
+            L->graph_exec[k] = nullptr;
+        }
+}
+
 static int set_device(axlb_lattice *L) {
     HIP_TRY(L, hipSetDevice(L->device));
     return AXLB_OK;
@@ -172,6 +181,27 @@ static int compute_fields(axlb_lattice *L) {
     else
         e = launch_fields(L->P, L->storage, 0, L->pop[par], L->lag[par], L->fld, L->stream);
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("fields launch: ") + hipGetErrorString(e));
+    return AXLB_OK;
+}
+
+int axlb::lattice_start(axlb_lattice *L) {
+    int rc = set_device(L);
+    if (rc) return rc;
+    if (!L->started) {
+        rc = check_bcs(L);
+        if (rc) return rc;
+        L->P = make_params(L);
+        L->started = true;
+    }
+    return AXLB_OK;
+}
+
+int axlb::lattice_step_once(axlb_lattice *L) {
+    int rc = lattice_start(L);
+    if (rc) return rc;
+    rc = launch_one(L, L->steps);
+    if (rc) return rc;
+    L->steps += 1;
     return AXLB_OK;
 }
 
@@ -338,6 +368,7 @@ int axlb_set_body_force(axlb_lattice *L, double g_axial, double T0) {
 int axlb_set_fields(axlb_lattice *L, const double *rho, const double *ur, const double *uz,
                     const double *uth, const double *T) {
     if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (L->batched) return fail(L, AXLB_ESTATE, "the lattice is in a batch");
     int rc = set_device(L);
     if (rc) return rc;
     const size_t N = (size_t)L->Nr * L->Nz;
@@ -366,15 +397,10 @@ int axlb_set_fields(axlb_lattice *L, const double *rho, const double *ur, const 
 int axlb_step(axlb_lattice *L, long n) {
     if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
     if (n < 0) return fail(L, AXLB_EINVAL, "negative step count");
+    if (L->batched) return fail(L, AXLB_ESTATE, "the lattice steps through its batch");
     if (n == 0) return AXLB_OK;
-    int rc = set_device(L);
+    int rc = lattice_start(L);
     if (rc) return rc;
-    if (!L->started) {
-        rc = check_bcs(L);
-        if (rc) return rc;
-        L->P = make_params(L);
-        L->started = true;
-    }
     while (n > 0) {
         if (n >= BUNDLE && L->use_graphs) {
             const int k = (int)(L->steps & 1);
@@ -486,9 +512,14 @@ int axlb_residual(axlb_lattice *L, double *r) {
         *r = INFINITY;
         return AXLB_OK;
     }
+    // velocity components against the speed field (a component may be zero
+    // up to round-off), T against itself
     double m = 0.0;
-    for (int c = 0; c < 4; ++c)
-        if (s[2 * c + 1] > 0.0) m = std::fmax(m, std::sqrt(s[2 * c]) / ((double)K * std::sqrt(s[2 * c + 1])));
+    const double speed2 = s[1] + s[3] + s[5];
+    if (speed2 > 0.0)
+        for (int c = 0; c < 3; ++c)
+            m = std::fmax(m, std::sqrt(s[2 * c]) / ((double)K * std::sqrt(speed2)));
+    if (s[7] > 0.0) m = std::fmax(m, std::sqrt(s[6]) / ((double)K * std::sqrt(s[7])));
     *r = m;
     return AXLB_OK;
 }
@@ -530,6 +561,7 @@ int axlb_save(axlb_lattice *L, void *host, size_t bytes) {
 
 int axlb_load(axlb_lattice *L, const void *host, size_t bytes) {
     if (!L || !host) return fail(L, AXLB_EINVAL, "NULL argument");
+    if (L->batched) return fail(L, AXLB_ESTATE, "the lattice is in a batch");
     size_t need;
     axlb_state_size(L, &need);
     Header h;
@@ -554,7 +586,7 @@ int axlb_load(axlb_lattice *L, const void *host, size_t bytes) {
 }
 
 void axlb_destroy(axlb_lattice *L) {
-    if (!L) return;
+    if (!L || L->batched) return;  // a member is released with its batch
     (void)hipSetDevice(L->device);
     if (L->stream) (void)hipStreamSynchronize(L->stream);
     for (int k = 0; k < 2; ++k)
@@ -562,6 +594,96 @@ void axlb_destroy(axlb_lattice *L) {
     if (L->own_mem && L->base) (void)hipFree(L->base);
     if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
     delete L;
+}
+
+int axlb_set_tile(axlb_lattice *L, int tile) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (L->batched) return fail(L, AXLB_ESTATE, "the lattice is in a batch");
+    if (tile < 0 || tile >= tile_count()) return fail(L, AXLB_EINVAL, "tile out of range");
+    if (tile != L->tile) {
+        int rc = set_device(L);
+        if (rc) return rc;
+        HIP_TRY(L, hipStreamSynchronize(L->stream));
+        drop_graphs(L);
+        L->tile = tile;
+    }
+    return AXLB_OK;
+}
+
+int axlb_get_tile(const axlb_lattice *L, int *tile, int *tile_r, int *tile_z) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    int bx, by;
+    tile_shape(L->tile, &bx, &by);
+    if (tile) *tile = L->tile;
+    if (tile_r) *tile_r = bx;
+    if (tile_z) *tile_z = by;
+    return AXLB_OK;
+}
+
+int axlb_tile_shape(int tile, int *tile_r, int *tile_z) {
+    if (tile < 0 || tile >= tile_count()) return fail(nullptr, AXLB_EINVAL, "tile out of range");
+    tile_shape(tile, tile_r, tile_z);
+    return AXLB_OK;
+}
+
+int axlb_autotune(axlb_lattice *L, int steps_per_trial, double *ms_per_step, int *best) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (L->batched) return fail(L, AXLB_ESTATE, "the lattice is in a batch");
+    if (steps_per_trial < 2) return fail(L, AXLB_EINVAL, "steps_per_trial must be >= 2");
+    int rc = lattice_start(L);
+    if (rc) return rc;
+    // the trials step the lattice: keep the state and restore it afterwards
+    const size_t pops = (L->layout == AXLB_LAYOUT_AB ? 2 : 1) * L->lay.pop_bytes;
+    const size_t bytes = pops + 2 * L->lay.lag_bytes;
+    char *keep = nullptr;
+    if (hipMalloc((void **)&keep, bytes) != hipSuccess) return fail(L, AXLB_ENOMEM, "autotune snapshot");
+    const long steps0 = L->steps;
+    const int tile0 = L->tile;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(keep);
+    };
+    // pop[0], (pop[1]), lag[0], lag[1] are consecutive in the lattice block
+    if (hipMemcpyAsync(keep, L->pop[0], bytes, hipMemcpyDeviceToDevice, L->stream) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(L, AXLB_EDEVICE, "autotune setup");
+    }
+    double best_ms = 1e300;
+    int best_tile = tile0;
+    for (int t = 0; t < tile_count(); ++t) {
+        L->tile = t;
+        int r2 = AXLB_OK;
+        for (int s = 0; s < 2 && r2 == AXLB_OK; ++s, ++L->steps) r2 = launch_one(L, L->steps);
+        (void)hipEventRecord(e0, L->stream);
+        for (int s = 0; s < steps_per_trial && r2 == AXLB_OK; ++s, ++L->steps) r2 = launch_one(L, L->steps);
+        (void)hipEventRecord(e1, L->stream);
+        float ms = 0.f;
+        if (r2 != AXLB_OK || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            L->tile = tile0;
+            cleanup();
+            return r2 != AXLB_OK ? r2 : fail(L, AXLB_EDEVICE, "autotune timing");
+        }
+        const double per = ms / steps_per_trial;
+        if (ms_per_step) ms_per_step[t] = per;
+        if (per < best_ms) {
+            best_ms = per;
+            best_tile = t;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(L->pop[0], keep, bytes, hipMemcpyDeviceToDevice, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    cleanup();
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, "autotune restore");
+    L->steps = steps0;
+    L->has_snap = false;
+    if (best_tile != L->tile || L->tile != tile0) drop_graphs(L);
+    L->tile = best_tile;
+    if (best) *best = best_tile;
+    return AXLB_OK;
 }
 
 const char *axlb_last_error(const axlb_lattice *L) {

@@ -1,0 +1,404 @@
+// Batched stepping of many independent lattices of uneven size: every step
+// of every member runs in one fused launch over a work-list of (member,
+// tile) pairs, 100-step bundles are captured as HIP graphs, and the tile
+// shape and the launch schedule come from an autotuner.  The node update is
+// the one of the single-lattice kernels (axlb_node.h), so a member's result
+// does not depend on whether it ran alone or in a batch.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/axlb.h"
+#include "axlb_internal.h"
+#include "axlb_launch.h"
+#include "axlb_node.h"
+
+namespace axlb {
+
+// Per-member descriptor in device memory.
+struct InstDesc {
+    KParams P;
+    void *pop;
+    float *lag[2];
+    int parity0;     // member step count at batch creation, mod 2
+    int tile_begin;  // first work-list entry of this member
+    int gx;          // tiles along r
+    int pad;
+};
+
+// Work-list entries are dealt to the 8 XCDs in 8 contiguous chunks, so that
+// the tiles of one member (and their neighbour rows) share an L2; within a
+// chunk the blocks of that XCD stride over the entries.  With as many blocks
+// as entries every block takes one tile; with fewer, blocks persist and loop.
+template <class S, int BX, int BY>
+__global__ void __launch_bounds__(BX *BY)
+    k_step_batch(const InstDesc *__restrict__ D, const int *__restrict__ tile_inst, int ntiles,
+                 int phase) {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int xcd = b & 7, k = b >> 3;
+    const int nbx = (G >> 3) + (xcd < (G & 7) ? 1 : 0);
+    const int lo = (int)((long long)ntiles * xcd / 8), hi = (int)((long long)ntiles * (xcd + 1) / 8);
+    for (int t = lo + k; t < hi; t += nbx) {
+        const InstDesc *d = D + tile_inst[t];
+        const int local = t - d->tile_begin;
+        const int j = (local % d->gx) * BX + (int)threadIdx.x % BX;
+        const int i = (local / d->gx) * BY + (int)threadIdx.x / BX;
+        if (i >= d->P.Nz || j >= d->P.Nr) continue;
+        S *A = (S *)d->pop;
+        if ((d->parity0 ^ phase) == 0)
+            update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j);
+        else
+            update_node<S, MODE_AA_EVEN>(d->P, A, A, d->lag[1], d->lag[0], i, j);
+    }
+}
+
+#define AXLB_BATCH_TILES(X) X(0, 64, 4) X(1, 64, 2) X(2, 64, 8) X(3, 128, 2) X(4, 256, 1) \
+    X(5, 64, 1) X(6, 128, 4) X(7, 32, 8)
+
+template <class S>
+static hipError_t launch_batch_t(int tile, int blocks, const InstDesc *D, const int *tiles,
+                                 int ntiles, int phase, hipStream_t st) {
+    switch (tile) {
+#define AXLB_CASE(id, bx, by)                                                               \
+    case id:                                                                                \
+        k_step_batch<S, bx, by><<<blocks, bx * by, 0, st>>>(D, tiles, ntiles, phase); \
+        break;
+        AXLB_BATCH_TILES(AXLB_CASE)
+#undef AXLB_CASE
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_batch(int storage, int tile, int blocks, const InstDesc *D,
+                               const int *tiles, int ntiles, int phase, hipStream_t st) {
+    if (storage == STORE_F16) return launch_batch_t<__half>(tile, blocks, D, tiles, ntiles, phase, st);
+    if (storage == STORE_BF16)
+        return launch_batch_t<__hip_bfloat16>(tile, blocks, D, tiles, ntiles, phase, st);
+    return launch_batch_t<float>(tile, blocks, D, tiles, ntiles, phase, st);
+}
+
+}  // namespace axlb
+
+using namespace axlb;
+
+struct axlb_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::vector<axlb_lattice *> members;
+    std::vector<hipStream_t> member_streams;
+    int storage = 0;
+    int tile = 0;
+    int blocks = 0;  // 0: one block per work-list entry; else persistent blocks
+    InstDesc *d_desc = nullptr;
+    int *d_tiles = nullptr;
+    int ntiles = 0;
+    long steps = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    std::string err;
+};
+
+static thread_local std::string g_batch_error;
+
+static int bfail(axlb_batch *b, int code, const std::string &m) {
+    if (b) b->err = m;
+    else g_batch_error = m;
+    return code;
+}
+
+#define BHIP(b, expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) return bfail(b, AXLB_EDEVICE, std::string(#expr) + ": " + \
+                                                               hipGetErrorString(e_));   \
+    } while (0)
+
+static void drop_batch_graphs(axlb_batch *b) {
+    for (int k = 0; k < 2; ++k)
+        if (b->graph[k]) {
+            (void)hipGraphExecDestroy(b->graph[k]);
+            b->graph[k] = nullptr;
+        }
+}
+
+// Descriptors and work-list for the current tile shape.
+static int build_worklist(axlb_batch *b) {
+    int bx, by;
+    tile_shape(b->tile, &bx, &by);
+    std::vector<InstDesc> desc(b->members.size());
+    std::vector<int> tiles;
+    for (size_t m = 0; m < b->members.size(); ++m) {
+        axlb_lattice *L = b->members[m];
+        InstDesc &d = desc[m];
+        std::memset(&d, 0, sizeof(d));
+        d.P = L->P;
+        d.pop = L->pop[0];
+        d.lag[0] = L->lag[0];
+        d.lag[1] = L->lag[1];
+        d.parity0 = (int)((L->steps - b->steps) & 1);
+        d.gx = (L->Nr + bx - 1) / bx;
+        const int gy = (L->Nz + by - 1) / by;
+        d.tile_begin = (int)tiles.size();
+        tiles.insert(tiles.end(), (size_t)d.gx * gy, (int)m);
+    }
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    b->d_desc = nullptr;
+    b->d_tiles = nullptr;
+    BHIP(b, hipMalloc((void **)&b->d_desc, desc.size() * sizeof(InstDesc)));
+    BHIP(b, hipMalloc((void **)&b->d_tiles, tiles.size() * sizeof(int)));
+    BHIP(b, hipMemcpyAsync(b->d_desc, desc.data(), desc.size() * sizeof(InstDesc),
+                           hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(int),
+                           hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    b->ntiles = (int)tiles.size();
+    drop_batch_graphs(b);
+    return AXLB_OK;
+}
+
+static int batch_launch(axlb_batch *b, long s) {
+    int blocks = b->blocks > 0 ? b->blocks : b->ntiles;
+    if (blocks < 8) blocks = 8;  // every XCD chunk needs a block
+    hipError_t e = launch_batch(b->storage, b->tile, blocks, b->d_desc, b->d_tiles, b->ntiles,
+                                (int)(s & 1), b->stream);
+    if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    return AXLB_OK;
+}
+
+static void advance_members(axlb_batch *b, long n) {
+    b->steps += n;
+    for (axlb_lattice *L : b->members) L->steps += n;
+}
+
+extern "C" {
+
+int axlb_batch_create(axlb_lattice *const *lats, int n, axlb_batch **out) {
+    if (!out) return bfail(nullptr, AXLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!lats || n <= 0) return bfail(nullptr, AXLB_EINVAL, "empty batch");
+    const int dev = lats[0] ? lats[0]->device : 0;
+    for (int m = 0; m < n; ++m) {
+        axlb_lattice *L = lats[m];
+        if (!L) return bfail(nullptr, AXLB_EINVAL, "NULL member");
+        if (L->device != dev) return bfail(nullptr, AXLB_EINVAL, "members on different devices");
+        if (L->layout != AXLB_LAYOUT_AA) return bfail(nullptr, AXLB_EINVAL, "batches need the AA layout");
+        if (L->storage != lats[0]->storage) return bfail(nullptr, AXLB_EINVAL, "mixed storage in a batch");
+        if (L->batched) return bfail(nullptr, AXLB_ESTATE, "lattice already in a batch");
+        for (int k = 0; k < m; ++k)
+            if (lats[k] == L) return bfail(nullptr, AXLB_EINVAL, "lattice listed twice");
+    }
+    axlb_batch *b = new (std::nothrow) axlb_batch();
+    if (!b) return bfail(nullptr, AXLB_ENOMEM, "host allocation failed");
+    b->device = dev;
+    b->storage = lats[0]->storage;
+    if (hipSetDevice(dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return bfail(nullptr, AXLB_EDEVICE, "stream creation failed");
+    }
+    for (int m = 0; m < n; ++m) {
+        axlb_lattice *L = lats[m];
+        // lock the boundary rules as a first step would
+        const int rc = lattice_start(L);
+        if (rc != AXLB_OK) {
+            const std::string msg = std::string("member ") + std::to_string(m) + ": " + L->err;
+            axlb_batch_destroy(b);
+            return bfail(nullptr, rc, msg);
+        }
+        (void)hipStreamSynchronize(L->stream);
+        b->members.push_back(L);
+        b->member_streams.push_back(L->stream);
+        L->stream = b->stream;  // all member work is ordered on the batch stream
+        L->batched = true;
+    }
+    int rc = build_worklist(b);
+    if (rc != AXLB_OK) {
+        const std::string msg = b->err;
+        axlb_batch_destroy(b);
+        return bfail(nullptr, rc, msg);
+    }
+    *out = b;
+    return AXLB_OK;
+}
+
+int axlb_batch_size(const axlb_batch *b, int *members, long long *nodes) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    long long s = 0;
+    for (const axlb_lattice *L : b->members) s += (long long)L->Nr * L->Nz;
+    if (members) *members = (int)b->members.size();
+    if (nodes) *nodes = s;
+    return AXLB_OK;
+}
+
+int axlb_batch_set_schedule(axlb_batch *b, int tile, int blocks) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    if (tile < 0 || tile >= tile_count() || blocks < 0) return bfail(b, AXLB_EINVAL, "bad schedule");
+    BHIP(b, hipSetDevice(b->device));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    const bool rebuild = tile != b->tile;
+    b->tile = tile;
+    b->blocks = blocks;
+    drop_batch_graphs(b);
+    return rebuild ? build_worklist(b) : AXLB_OK;
+}
+
+int axlb_batch_get_schedule(const axlb_batch *b, int *tile, int *blocks) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    if (tile) *tile = b->tile;
+    if (blocks) *blocks = b->blocks;
+    return AXLB_OK;
+}
+
+int axlb_batch_step(axlb_batch *b, long n) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    if (n < 0) return bfail(b, AXLB_EINVAL, "negative step count");
+    BHIP(b, hipSetDevice(b->device));
+    while (n > 0) {
+        if (n >= BUNDLE) {
+            const int k = (int)(b->steps & 1);
+            if (!b->graph[k]) {
+                BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                int rc = AXLB_OK;
+                for (long s = 0; s < BUNDLE && rc == AXLB_OK; ++s) rc = batch_launch(b, k + s);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(b->stream, &g);
+                if (rc != AXLB_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, "batch graph capture failed");
+                e = hipGraphInstantiate(&b->graph[k], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    b->graph[k] = nullptr;
+                    return bfail(b, AXLB_EDEVICE, "batch graph instantiate failed");
+                }
+            }
+            BHIP(b, hipGraphLaunch(b->graph[k], b->stream));
+            advance_members(b, BUNDLE);
+            n -= BUNDLE;
+        } else {
+            int rc = batch_launch(b, b->steps);
+            if (rc) return rc;
+            advance_members(b, 1);
+            n -= 1;
+        }
+    }
+    return AXLB_OK;
+}
+
+int axlb_batch_sync(axlb_batch *b) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    BHIP(b, hipSetDevice(b->device));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    return AXLB_OK;
+}
+
+int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step, int *best_tile,
+                        int *best_blocks) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    if (steps_per_trial < 2) return bfail(b, AXLB_EINVAL, "steps_per_trial must be >= 2");
+    BHIP(b, hipSetDevice(b->device));
+    int dev_cu = 0;
+    BHIP(b, hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, b->device));
+    const int sched[AXLB_NSCHEDULES] = {0, 4 * dev_cu, 8 * dev_cu, 16 * dev_cu};
+    // keep every member's state; the trials step them
+    std::vector<char *> keep(b->members.size(), nullptr);
+    auto release = [&]() {
+        for (char *p : keep)
+            if (p) (void)hipFree(p);
+    };
+    for (size_t m = 0; m < b->members.size(); ++m) {
+        axlb_lattice *L = b->members[m];
+        const size_t bytes = L->lay.pop_bytes + 2 * L->lay.lag_bytes;
+        if (hipMalloc((void **)&keep[m], bytes) != hipSuccess) {
+            release();
+            return bfail(b, AXLB_ENOMEM, "autotune snapshot");
+        }
+        BHIP(b, hipMemcpyAsync(keep[m], L->pop[0], bytes, hipMemcpyDeviceToDevice, b->stream));
+    }
+    hipEvent_t e0, e1;
+    BHIP(b, hipEventCreate(&e0));
+    BHIP(b, hipEventCreate(&e1));
+    const long steps0 = b->steps;
+    double best_ms = 1e300;
+    int bt = b->tile, bb = b->blocks, rc = AXLB_OK;
+    for (int t = 0; t < tile_count() && rc == AXLB_OK; ++t) {
+        b->tile = t;
+        rc = build_worklist(b);
+        for (int sidx = 0; sidx < AXLB_NSCHEDULES && rc == AXLB_OK; ++sidx) {
+            b->blocks = sched[sidx];
+            for (int s = 0; s < 2 && rc == AXLB_OK; ++s, ++b->steps) rc = batch_launch(b, b->steps);
+            (void)hipEventRecord(e0, b->stream);
+            for (int s = 0; s < steps_per_trial && rc == AXLB_OK; ++s, ++b->steps)
+                rc = batch_launch(b, b->steps);
+            (void)hipEventRecord(e1, b->stream);
+            float ms = 0.f;
+            if (rc == AXLB_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = bfail(b, AXLB_EDEVICE, "autotune timing");
+            const double per = ms / steps_per_trial;
+            if (ms_per_step) ms_per_step[t * AXLB_NSCHEDULES + sidx] = per;
+            if (rc == AXLB_OK && per < best_ms) {
+                best_ms = per;
+                bt = t;
+                bb = sched[sidx];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore every member and the batch step count
+    for (size_t m = 0; m < b->members.size(); ++m) {
+        axlb_lattice *L = b->members[m];
+        const size_t bytes = L->lay.pop_bytes + 2 * L->lay.lag_bytes;
+        (void)hipMemcpyAsync(L->pop[0], keep[m], bytes, hipMemcpyDeviceToDevice, b->stream);
+    }
+    (void)hipStreamSynchronize(b->stream);
+    release();
+    b->steps = steps0;
+    if (rc != AXLB_OK) return rc;
+    b->tile = bt;
+    b->blocks = bb;
+    rc = build_worklist(b);
+    if (rc != AXLB_OK) return rc;
+    if (best_tile) *best_tile = bt;
+    if (best_blocks) *best_blocks = bb;
+    return AXLB_OK;
+}
+
+void axlb_batch_destroy(axlb_batch *b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_batch_graphs(b);
+    for (size_t m = 0; m < b->members.size(); ++m) {
+        b->members[m]->stream = b->member_streams[m];
+        b->members[m]->batched = false;
+    }
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char *axlb_batch_last_error(const axlb_batch *b) {
+    return b ? b->err.c_str() : g_batch_error.c_str();
+}
+
+int axlb_step_each(axlb_lattice *const *lats, int n, long steps) {
+    if (!lats || n <= 0 || steps < 0) return bfail(nullptr, AXLB_EINVAL, "bad arguments");
+    for (long s = 0; s < steps; ++s)
+        for (int m = 0; m < n; ++m) {
+            if (!lats[m] || lats[m]->batched) return bfail(nullptr, AXLB_EINVAL, "bad member");
+            const int rc = lattice_step_once(lats[m]);
+            if (rc != AXLB_OK) return bfail(nullptr, rc, lats[m]->err);
+        }
+    return AXLB_OK;
+}
+
+}  // extern "C"

@@ -42,7 +42,9 @@ struct axlb_lattice {
     double *fld = nullptr, *snap = nullptr, *red = nullptr;
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     bool use_graphs = true;
+    int tile = 0;  // step-kernel tile shape (see tile_shape)
     bool started = false, has_snap = false;
+    bool batched = false;  // member of an axlb_batch: steps through the batch
     long steps = 0, snap_step = 0;
     axlb::KParams P{};
     std::string err;
@@ -50,4 +52,8 @@ struct axlb_lattice {
 
 namespace axlb {
 KParams make_params(const axlb_lattice *L);
+// Checks and locks the boundary rules (as the first step does).
+int lattice_start(axlb_lattice *L);
+// One step as a plain kernel launch on the lattice's stream.
+int lattice_step_once(axlb_lattice *L);
 }

@@ -10,8 +10,13 @@ namespace axlb {
 
 enum { STORE_F32 = 0, STORE_F16 = 1, STORE_BF16 = 2 };
 
+// Tile shapes of the step kernel: tile_shape(t) gives r x z nodes per workgroup.
+constexpr int NTILES = 8;
+int tile_count();
+void tile_shape(int tile, int *bx, int *by);
+
 // mode: 0 = AB pull (src -> dst), 1 = AA odd phase, 2 = AA even phase (src == dst).
-hipError_t launch_step(const KParams &P, int storage, int mode, void *src, void *dst,
+hipError_t launch_step(const KParams &P, int storage, int tile, int mode, void *src, void *dst,
                        const float *Mprev, float *Mnext, hipStream_t st);
 hipError_t launch_fields(const KParams &P, int storage, int mode, const void *src,
                          const float *Mprev, double *out, hipStream_t st);

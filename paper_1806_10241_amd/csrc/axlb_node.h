@@ -1,0 +1,563 @@
+// Device code of one node update of the axisymmetric cascaded LB step
+// (arXiv 1806.10241, Section 2), shared by the single-lattice and the batched
+// kernels so that both perform identical arithmetic.  Internal.
+#pragma once
+
+#include "axlb_device.h"
+
+namespace axlb {
+
+// ----------------------------------------------------------------------------
+// Lattices.  D2Q9 velocities in the order of Section 2.2, eq. (10); D2Q5 in
+// the order of eq. (28).
+template <int FLD> struct Lat;
+template <> struct Lat<FLOW> {
+    static constexpr int NQ = 9, OFF = 0;
+    __host__ __device__ static constexpr int ex(int q) {
+        return q == 1 || q == 5 || q == 8 ? 1 : (q == 3 || q == 6 || q == 7 ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int ey(int q) {
+        return q == 2 || q == 5 || q == 6 ? 1 : (q == 4 || q == 7 || q == 8 ? -1 : 0);
+    }
+    __host__ __device__ static constexpr int opp(int q) {
+        return q == 0 ? 0 : (q <= 4 ? (q + 1) % 4 + 1 : (q + 1) % 4 + 5);
+    }
+    __host__ __device__ static constexpr int refl(int q) {  // e_y -> -e_y
+        return q == 2 ? 4 : q == 4 ? 2 : q == 5 ? 8 : q == 8 ? 5 : q == 6 ? 7 : q == 7 ? 6 : q;
+    }
+};
+template <int OFFSET> struct Lat5 {
+    static constexpr int NQ = 5, OFF = OFFSET;
+    __host__ __device__ static constexpr int ex(int q) { return q == 1 ? 1 : (q == 3 ? -1 : 0); }
+    __host__ __device__ static constexpr int ey(int q) { return q == 2 ? 1 : (q == 4 ? -1 : 0); }
+    __host__ __device__ static constexpr int opp(int q) { return q == 0 ? 0 : (q + 1) % 4 + 1; }
+    __host__ __device__ static constexpr int refl(int q) { return q == 2 ? 4 : q == 4 ? 2 : q; }
+};
+template <> struct Lat<SWIRL> : Lat5<GOFF> {};
+template <> struct Lat<THERMAL> : Lat5<HOFF> {};
+
+static_assert(Lat<FLOW>::opp(1) == 3 && Lat<FLOW>::opp(2) == 4 && Lat<FLOW>::opp(5) == 7 &&
+                  Lat<FLOW>::opp(6) == 8 && Lat<FLOW>::opp(8) == 6,
+              "D2Q9 opposite table");
+static_assert(Lat<SWIRL>::opp(1) == 3 && Lat<SWIRL>::opp(4) == 2, "D2Q5 opposite table");
+
+// Key of population plane q at node (i, j) for the stochastic rounding of
+// 16-bit stores (unused for FP32).
+__device__ __forceinline__ unsigned skey(int i, int j, int q) {
+    return ((unsigned)i * 0x9E3779B1U) ^ ((unsigned)j * 0x85EBCA77U) ^ ((unsigned)q * 0xC2B2AE3DU);
+}
+
+__device__ __forceinline__ bool is_wall(int k) {
+    return k == NOSLIP || k == DIRICHLET || k == OMEGA_R || k == ADIABATIC;
+}
+
+// Value that the advection-diffusion wall rule imposes (psi_w = u_theta,w
+// with rho_0 = 1, or T_w - T_ref in shifted storage); ym is the radius where
+// the link crosses the wall.
+template <int FLD>
+__device__ __forceinline__ float wall_value(const KParams &P, int face, float ym) {
+    const int k = kind_of(P, face, FLD);
+    const float v = val_of<FLD>(P, face);
+    float s = k == DIRICHLET ? v : (k == OMEGA_R ? v * ym : 0.f);
+    if (FLD == THERMAL) s -= P.Tref;
+    return s;
+}
+
+// ----------------------------------------------------------------------------
+// Pull of population Q of distribution FLD into node (i, j) when the source
+// node (i - e_x, j - e_y) lies outside the fluid.  Precedence per link: a
+// solid wall (radial faces first) -> half-way bounce-back for f and for zero
+// flux, anti-bounce-back -v + 2 w s_w (w = 1/6) for an imposed u_theta or T;
+// then the axis -> specular reflection from the node shifted by e_x, with a
+// sign change for g (u_theta is odd); then the periodic wrap along z.
+// AA selects the slot convention of the odd phase of the in-place layout.
+template <class S, bool AA, int FLD, int Q>
+__device__ __forceinline__ float pull_edge(const KParams &P, const S *A, int i, int j) {
+    using L = Lat<FLD>;
+    constexpr int ex = L::ex(Q), ey = L::ey(Q);
+    int si = i - ex, sj = j - ey;
+    const int fy = sj < 0 ? R_IN : (sj >= P.Nr ? R_OUT : -1);
+    const int fx = si < 0 ? Z_LO : (si >= P.Nz ? Z_HI : -1);
+    int wall = -1;
+    if (fy >= 0 && is_wall(kind_of(P, fy, FLD))) wall = fy;
+    else if (fx >= 0 && is_wall(kind_of(P, fx, FLD))) wall = fx;
+    if (wall >= 0) {
+        // f*_{opp Q}(i, j): AB keeps it in plane opp Q, the even AA phase put
+        // it into plane Q.
+        constexpr int slot = AA ? Q : L::opp(Q);
+        const float v = Conv<S>::ld(A + (L::OFF + slot) * P.plane + (long long)i * P.pitch + j);
+        if (FLD == FLOW || kind_of(P, wall, FLD) == ADIABATIC) return v;
+        const float ym = P.r0 + (float)j + 0.5f - 0.5f * (float)ey;
+        return -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
+    }
+    float sign = 1.f;
+    int qs = Q;
+    if (fy >= 0) {  // only the axis remains on a radial face
+        qs = L::refl(Q);
+        sj = j;
+        if (FLD == SWIRL) sign = -1.f;
+    }
+    if (fx >= 0) si += si < 0 ? P.Nz : -P.Nz;  // periodic
+    const int slot = AA ? L::opp(qs) : qs;
+    return sign * Conv<S>::ld(A + (L::OFF + slot) * P.plane + (long long)si * P.pitch + sj);
+}
+
+template <class S, bool AA, int FLD, int Q>
+__device__ __forceinline__ float pull(const KParams &P, const S *A, int i, int j) {
+    using L = Lat<FLD>;
+    constexpr int ex = L::ex(Q), ey = L::ey(Q);
+    const int si = i - ex, sj = j - ey;
+    if ((unsigned)si < (unsigned)P.Nz && (unsigned)sj < (unsigned)P.Nr) {
+        constexpr int slot = AA ? L::opp(Q) : Q;
+        return Conv<S>::ld(A + (L::OFF + slot) * P.plane + (long long)si * P.pitch + sj);
+    }
+    return pull_edge<S, AA, FLD, Q>(P, A, i, j);
+}
+
+// Odd AA phase: post-collision f*_Q(i, j) = v goes to the slot from which
+// the next (even) phase reads it, by the same rules as pull_edge.
+template <class S, int FLD, int Q>
+__device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, float v) {
+    using L = Lat<FLD>;
+    constexpr int ex = L::ex(Q), ey = L::ey(Q);
+    int ti = i + ex;
+    const int tj = j + ey;
+    const int fy = tj < 0 ? R_IN : (tj >= P.Nr ? R_OUT : -1);
+    const int fx = ti < 0 ? Z_LO : (ti >= P.Nz ? Z_HI : -1);
+    int wall = -1;
+    if (fy >= 0 && is_wall(kind_of(P, fy, FLD))) wall = fy;
+    else if (fx >= 0 && is_wall(kind_of(P, fx, FLD))) wall = fx;
+    if (wall >= 0) {
+        float w = v;
+        if (FLD != FLOW && kind_of(P, wall, FLD) != ADIABATIC) {
+            const float ym = P.r0 + (float)j + 0.5f + 0.5f * (float)ey;
+            w = -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
+        }
+        Conv<S>::st(A + (L::OFF + L::opp(Q)) * P.plane + (long long)i * P.pitch + j, w,
+                    skey(i, j, L::OFF + Q));
+        return;
+    }
+    if (fy >= 0) {  // axis: arrives at (i + e_x, j) with e_y reversed
+        if (ti < 0) ti += P.Nz;
+        else if (ti >= P.Nz) ti -= P.Nz;
+        Conv<S>::st(A + (L::OFF + L::refl(Q)) * P.plane + (long long)ti * P.pitch + j,
+                    FLD == SWIRL ? -v : v, skey(i, j, L::OFF + Q));
+        return;
+    }
+    ti += ti < 0 ? P.Nz : -P.Nz;  // periodic
+    Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, v,
+                skey(i, j, L::OFF + Q));
+}
+
+template <class S, int FLD, int Q>
+__device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float v) {
+    using L = Lat<FLD>;
+    constexpr int ex = L::ex(Q), ey = L::ey(Q);
+    const int ti = i + ex, tj = j + ey;
+    if ((unsigned)ti < (unsigned)P.Nz && (unsigned)tj < (unsigned)P.Nr) {
+        Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, v,
+                    skey(i, j, L::OFF + Q));
+        return;
+    }
+    push_edge<S, FLD, Q>(P, A, i, j, v);
+}
+
+// ----------------------------------------------------------------------------
+// Lagged derivative field v (0 u_x, 1 u_y, 2 u_theta, 3 T - T_ref) at the
+// neighbour (i + di, j + dj); outside the fluid a ghost value mirrored
+// through the half-way wall: -q for u_x, u_y at a no-slip wall, 2 q_w - q
+// for an imposed u_theta or T, q for zero flux; q (u_x, T) or -q (u_y,
+// u_theta) at the axis; the wrapped node on a periodic face.
+__device__ __forceinline__ float lag_edge(const KParams &P, const float *M, int v, int i, int j,
+                                       int di, int dj) {
+    const int ni = i + di, nj = j + dj;
+    const float q1 = M[v * P.plane + (long long)i * P.pitch + j];
+    const int face = nj < 0 ? R_IN : (nj >= P.Nr ? R_OUT : (ni < 0 ? Z_LO : Z_HI));
+    const int fld = v <= 1 ? FLOW : (v == 2 ? SWIRL : THERMAL);
+    const int k = kind_of(P, face, fld);
+    if (k == PERIODIC) {
+        const int wi = ni < 0 ? ni + P.Nz : ni - P.Nz;
+        return M[v * P.plane + (long long)wi * P.pitch + nj];
+    }
+    if (k == MIRROR) return (v == 0 || v == 3) ? q1 : -q1;
+    if (k == ADIABATIC) return q1;
+    if (v <= 1) return -q1;
+    const float yw = P.r0 + (float)j + 0.5f + 0.5f * (float)dj;
+    const float s = v == 2 ? wall_value<SWIRL>(P, face, yw) : wall_value<THERMAL>(P, face, yw);
+    return 2.f * s - q1;
+}
+
+__device__ __forceinline__ float lag(const KParams &P, const float *M, int v, int i, int j, int di,
+                                     int dj) {
+    const int ni = i + di, nj = j + dj;
+    if ((unsigned)ni < (unsigned)P.Nz && (unsigned)nj < (unsigned)P.Nr)
+        return M[v * P.plane + (long long)ni * P.pitch + nj];
+    return lag_edge(P, M, v, i, j, di, dj);
+}
+
+// ----------------------------------------------------------------------------
+// The pre-collision half step (eq. 21, 38, 48) with the geometric sources of
+// eq. (4), (7), (9) and the body force of eq. (5) evaluated at that same
+// half-step state: the relations are solved per node, the terms linear in
+// the unknowns on the left and a few fixed-point sweeps for the weak
+// remainder.  Everything is carried as increments (half of each source) so
+// that a source of 1e-8 is not lost against O(1) fields in FP32.
+struct Half {
+    float drho, irho, ux, uy, psi, dphi;  // state seen by the collision (rho = 1 + drho)
+    float hMA, hFx, hFy, hSpsi, hSphi;    // half of each source
+};
+
+constexpr int HALF_SWEEPS = 3;
+
+// Reciprocal by the hardware instruction (within 1 ulp): the half step only
+// needs FP32 accuracy, and IEEE division costs ~10 instructions each.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ Half half_step(const KParams &P, float iy, float drho_o, float jx_o,
+                                          float jy_o, float psi_o, float dphi_o, const float d[5]) {
+    const float nu = P.nu, iy2 = iy * iy;
+    const float rho_o = 1.f + drho_o;
+    const float nuiy2 = nu * iy2;
+    const float ify = rcp(1.f + nuiy2);  // F_y terms linear in rho u_y
+    const float sy2 = nu * d[2] * iy, st2 = 0.5f * nu * d[3] * iy;
+    float hMA = 0.f, hFy = 0.f, hSpsi = 0.f;
+    float Jy = jy_o, rho = rho_o, psi = psi_o;
+#pragma unroll
+    for (int it = 0; it < HALF_SWEEPS; ++it) {
+        hMA = -0.5f * Jy * iy;                      // M^A/2 = -rho u_y/(2y)
+        rho = rho_o + hMA;
+        const float irho = rcp(rho);
+        const float a = Jy * irho * iy + 0.5f * nuiy2;  // S_psi terms linear in psi
+        hSpsi = (rho * st2 - psi_o * a) * rcp(1.f + a);
+        psi = psi_o + hSpsi;
+        hFy = (0.5f * (psi * psi - Jy * Jy) * irho * iy + rho * sy2 - nuiy2 * jy_o) * ify;
+        Jy = jy_o + hFy;
+    }
+    hMA = -0.5f * Jy * iy;
+    rho = rho_o + hMA;
+    const float irho = rcp(rho);
+    const float b = 0.5f * Jy * irho * iy;  // terms linear in phi and in rho u_x
+    const float ib = rcp(1.f + b);
+    const float phi_o = P.Tref + dphi_o;
+    const float hSphi = (0.5f * P.alpha * d[4] * iy - phi_o * b) * ib;
+    const float dphi = dphi_o + hSphi;
+    const float Fb = P.g_axial + P.gbeta * (P.Tref - P.T0 + dphi);
+    const float hFx = (0.5f * (rho * nu * (d[0] + d[1]) * iy + Fb) - jx_o * b) * ib;
+    Half H;
+    H.drho = drho_o + hMA;
+    H.irho = irho;
+    H.ux = (jx_o + hFx) * irho;
+    H.uy = Jy * irho;
+    H.psi = psi;
+    H.dphi = dphi;
+    H.hMA = hMA; H.hFx = hFx; H.hFy = hFy; H.hSpsi = hSpsi; H.hSphi = hSphi;
+    return H;
+}
+
+// Cascaded D2Q9 collision, eq. (17), with the source moments of eq. (26)
+// (p_0 = M^A/9, p_1 = F_x/6, p_2 = F_y/6) and f^p = f + K p (eq. 16a, 27).
+// f holds shifted populations f - w_q; with rho = 1 + drho the constant parts
+// of the raw moments (1/3 for xx, yy; 1/9 for xxyy) cancel against the
+// equilibrium terms in closed form, leaving only small quantities.
+__device__ __forceinline__ void collide_f(const KParams &P, float (&f)[9], const Half &H) {
+    const float ux = H.ux, uy = H.uy, drho = H.drho, rho = 1.f + drho;
+    const float ux2 = ux * ux, uy2 = uy * uy;
+    const float kxx = f[1] + f[3] + f[5] + f[6] + f[7] + f[8];
+    const float kyy = f[2] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const float kxy = f[5] - f[6] + f[7] - f[8];
+    const float kxxy = f[5] + f[6] - f[7] - f[8];
+    const float kxyy = f[5] - f[6] - f[7] + f[8];
+    const float kxxyy = f[5] + f[6] + f[7] + f[8];
+    const float p0 = (2.f / 9.f) * H.hMA;
+    const float p1 = (1.f / 3.f) * H.hFx;
+    const float p2 = (1.f / 3.f) * H.hFy;
+    const float p3 = P.om3 * (1.f / 12.f) * ((2.f / 3.f) * drho + rho * (ux2 + uy2) - (kxx + kyy));
+    const float p4 = P.om45 * 0.25f * (rho * (ux2 - uy2) - (kxx - kyy));
+    const float p5 = P.om45 * 0.25f * (rho * ux * uy - kxy);
+    const float p6 = P.om6 * 0.25f * (2.f * rho * ux2 * uy + kxxy - 2.f * ux * kxy -
+                                      uy * ((1.f / 3.f) + kxx)) -
+                     0.5f * uy * (3.f * p3 + p4) - 2.f * ux * p5;
+    const float p7 = P.om7 * 0.25f * (2.f * rho * ux * uy2 + kxyy - 2.f * uy * kxy -
+                                      ux * ((1.f / 3.f) + kyy)) -
+                     0.5f * ux * (3.f * p3 - p4) - 2.f * uy * p5;
+    const float p8 =
+        P.om8 * 0.25f *
+            ((1.f / 9.f) * drho + 3.f * rho * ux2 * uy2 -
+             (kxxyy - 2.f * ux * kxyy - 2.f * uy * kxxy + ux2 * ((1.f / 3.f) + kyy) +
+              uy2 * ((1.f / 3.f) + kxx) + 4.f * ux * uy * kxy)) -
+        2.f * p3 - 0.5f * uy2 * (3.f * p3 + p4) - 0.5f * ux2 * (3.f * p3 - p4) -
+        4.f * ux * uy * p5 - 2.f * uy * p6 - 2.f * ux * p7;
+    f[0] += p0 - 4.f * (p3 - p8);
+    f[1] += p0 + p1 - p3 + p4 + 2.f * (p7 - p8);
+    f[2] += p0 + p2 - p3 - p4 + 2.f * (p6 - p8);
+    f[3] += p0 - p1 - p3 + p4 - 2.f * (p7 + p8);
+    f[4] += p0 - p2 - p3 - p4 - 2.f * (p6 + p8);
+    f[5] += p0 + p1 + p2 + 2.f * p3 + p5 - p6 - p7 + p8;
+    f[6] += p0 - p1 + p2 + 2.f * p3 - p5 - p6 + p7 + p8;
+    f[7] += p0 - p1 - p2 + 2.f * p3 + p5 + p6 + p7 + p8;
+    f[8] += p0 + p1 - p2 + 2.f * p3 - p5 + p6 - p7 + p8;
+}
+
+// Cascaded D2Q5 collision for an advected scalar s = s_ref + ds stored as
+// g - w_q s_ref (eq. 34 for psi with s_ref = 0, eq. 49 for T with s_ref =
+// T_ref): relaxation of the central moments of eq. (31)/(43) to their
+// Maxwellian values gives a minus sign in front of |u|^2 s and
+// (u_x^2 - u_y^2) s.  Source moment q_0 = S/5 (eq. 41, 51), g^p = g + L q
+// (eq. 42, 52).
+__device__ __forceinline__ void collide_adv(float (&g)[5], float ux, float uy, float s,
+                                            float ds, float hS, float o12, float o3, float o4) {
+    const float kx = g[1] - g[3], ky = g[2] - g[4];
+    const float kxx = g[1] + g[3], kyy = g[2] + g[4];
+    const float q0 = 0.4f * hS;
+    const float q1 = 0.5f * o12 * (s * ux - kx);
+    const float q2 = 0.5f * o12 * (s * uy - ky);
+    const float q3 = 0.25f * o3 *
+                         ((2.f / 3.f) * ds - (kxx + kyy) + 2.f * (ux * kx + uy * ky) -
+                          (ux * ux + uy * uy) * s) +
+                     ux * q1 + uy * q2;
+    const float q4 = 0.25f * o4 *
+                         (-(kxx - kyy) + 2.f * (ux * kx - uy * ky) - (ux * ux - uy * uy) * s) +
+                     ux * q1 - uy * q2;
+    g[0] += q0 - 4.f * q3;
+    g[1] += q0 + q1 + q3 + q4;
+    g[2] += q0 + q2 + q3 - q4;
+    g[3] += q0 - q1 + q3 + q4;
+    g[4] += q0 - q2 + q3 - q4;
+}
+
+// Output moments (eq. 18, 35, 47) and central differences of the lagged
+// fields for node (i, j).
+struct Moments {
+    float drho, jx, jy, psi, dphi;
+};
+
+__device__ __forceinline__ Moments moments(const float (&f)[9], const float (&g)[5],
+                                           const float (&h)[5]) {
+    Moments m;
+    m.drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    m.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    m.jy = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
+    m.psi = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    m.dphi = (h[0] + h[1]) + (h[2] + h[3]) + h[4];
+    return m;
+}
+
+__device__ __forceinline__ void derivatives(const KParams &P, const float *M, int i, int j,
+                                            bool interior, float d[5]) {
+    if (interior) {
+        // all four neighbours are fluid nodes: plain loads at 32-bit offsets
+        const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j, w = (unsigned)P.pitch;
+        const float *Mx = M, *My = M + P.plane, *Mt = M + 2 * P.plane, *Mp = M + 3 * P.plane;
+        d[0] = 0.5f * (My[n + w] - My[n - w]);
+        d[1] = 0.5f * (Mx[n + 1] - Mx[n - 1]);
+        d[2] = 0.5f * (My[n + 1] - My[n - 1]);
+        d[3] = 0.5f * (Mt[n + 1] - Mt[n - 1]);
+        d[4] = 0.5f * (Mp[n + 1] - Mp[n - 1]);
+        return;
+    }
+    d[0] = 0.5f * (lag(P, M, 1, i, j, +1, 0) - lag(P, M, 1, i, j, -1, 0));  // d_x u_y
+    d[1] = 0.5f * (lag(P, M, 0, i, j, 0, +1) - lag(P, M, 0, i, j, 0, -1));  // d_y u_x
+    d[2] = 0.5f * (lag(P, M, 1, i, j, 0, +1) - lag(P, M, 1, i, j, 0, -1));  // d_y u_y
+    d[3] = 0.5f * (lag(P, M, 2, i, j, 0, +1) - lag(P, M, 2, i, j, 0, -1));  // d_y u_theta
+    d[4] = 0.5f * (lag(P, M, 3, i, j, 0, +1) - lag(P, M, 3, i, j, 0, -1));  // d_y T
+}
+
+// ----------------------------------------------------------------------------
+// Tile mapping: a workgroup updates TX x TY nodes (r x z), one node per
+// thread; with TX >= 64 a wavefront spans 64 consecutive r, so every plane
+// access is one contiguous 256-byte run in FP32.  Consecutive workgroup ids
+// are dealt round-robin over the 8 XCDs; they are remapped so that each XCD
+// owns one contiguous band of tiles and the neighbour rows an update touches
+// stay in that XCD's L2.
+constexpr int TX = 64, TY = 4;  // tile of the field, init and default step kernels
+
+template <int BX, int BY>
+__device__ __forceinline__ void tile_of(const KParams &P, int &i, int &j) {
+    const int gx = (P.Nr + BX - 1) / BX;
+    const int gy = (P.Nz + BY - 1) / BY;
+    const int nb = gx * gy;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, k = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    const int t = xcd * q + (xcd < r ? xcd : r) + k;
+    j = (t % gx) * BX + (int)threadIdx.x % BX;
+    i = (t / gx) * BY + (int)threadIdx.x / BX;
+}
+
+enum Mode { MODE_AB = 0, MODE_AA_ODD = 1, MODE_AA_EVEN = 2 };
+
+// Interior pull: the source node n - e_q is a fluid node (32-bit offsets
+// against a uniform plane base).
+template <class S, bool AA, int FLD, int Q>
+__device__ __forceinline__ float pull_in(const KParams &P, const S *A, unsigned n) {
+    using L = Lat<FLD>;
+    constexpr int slot = AA ? L::opp(Q) : Q;
+    const unsigned dn = (unsigned)(L::ex(Q) * P.pitch + L::ey(Q));
+    return Conv<S>::ld(A + (long long)(L::OFF + slot) * P.plane + (n - dn));
+}
+
+template <class S, int FLD, int Q>
+__device__ __forceinline__ void push_in(const KParams &P, S *A, unsigned n, int i, int j, float v) {
+    using L = Lat<FLD>;
+    const unsigned dn = (unsigned)(L::ex(Q) * P.pitch + L::ey(Q));
+    Conv<S>::st(A + (long long)(L::OFF + Q) * P.plane + (n + dn), v, skey(i, j, L::OFF + Q));
+}
+
+template <class S, int MODE>
+__device__ __forceinline__ void gather(const KParams &P, const S *A, int i, int j, bool interior,
+                                       float (&f)[9], float (&g)[5], float (&h)[5]) {
+    const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+    if (MODE == MODE_AA_EVEN) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) f[q] = Conv<S>::ld(A + (long long)q * P.plane + n);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            g[q] = Conv<S>::ld(A + (long long)(GOFF + q) * P.plane + n);
+            h[q] = Conv<S>::ld(A + (long long)(HOFF + q) * P.plane + n);
+        }
+        return;
+    }
+    constexpr bool AA = MODE == MODE_AA_ODD;
+    if (interior) {
+        f[0] = pull_in<S, AA, FLOW, 0>(P, A, n);
+        f[1] = pull_in<S, AA, FLOW, 1>(P, A, n);
+        f[2] = pull_in<S, AA, FLOW, 2>(P, A, n);
+        f[3] = pull_in<S, AA, FLOW, 3>(P, A, n);
+        f[4] = pull_in<S, AA, FLOW, 4>(P, A, n);
+        f[5] = pull_in<S, AA, FLOW, 5>(P, A, n);
+        f[6] = pull_in<S, AA, FLOW, 6>(P, A, n);
+        f[7] = pull_in<S, AA, FLOW, 7>(P, A, n);
+        f[8] = pull_in<S, AA, FLOW, 8>(P, A, n);
+        g[0] = pull_in<S, AA, SWIRL, 0>(P, A, n);
+        g[1] = pull_in<S, AA, SWIRL, 1>(P, A, n);
+        g[2] = pull_in<S, AA, SWIRL, 2>(P, A, n);
+        g[3] = pull_in<S, AA, SWIRL, 3>(P, A, n);
+        g[4] = pull_in<S, AA, SWIRL, 4>(P, A, n);
+        h[0] = pull_in<S, AA, THERMAL, 0>(P, A, n);
+        h[1] = pull_in<S, AA, THERMAL, 1>(P, A, n);
+        h[2] = pull_in<S, AA, THERMAL, 2>(P, A, n);
+        h[3] = pull_in<S, AA, THERMAL, 3>(P, A, n);
+        h[4] = pull_in<S, AA, THERMAL, 4>(P, A, n);
+        return;
+    }
+    f[0] = pull<S, AA, FLOW, 0>(P, A, i, j);
+    f[1] = pull<S, AA, FLOW, 1>(P, A, i, j);
+    f[2] = pull<S, AA, FLOW, 2>(P, A, i, j);
+    f[3] = pull<S, AA, FLOW, 3>(P, A, i, j);
+    f[4] = pull<S, AA, FLOW, 4>(P, A, i, j);
+    f[5] = pull<S, AA, FLOW, 5>(P, A, i, j);
+    f[6] = pull<S, AA, FLOW, 6>(P, A, i, j);
+    f[7] = pull<S, AA, FLOW, 7>(P, A, i, j);
+    f[8] = pull<S, AA, FLOW, 8>(P, A, i, j);
+    g[0] = pull<S, AA, SWIRL, 0>(P, A, i, j);
+    g[1] = pull<S, AA, SWIRL, 1>(P, A, i, j);
+    g[2] = pull<S, AA, SWIRL, 2>(P, A, i, j);
+    g[3] = pull<S, AA, SWIRL, 3>(P, A, i, j);
+    g[4] = pull<S, AA, SWIRL, 4>(P, A, i, j);
+    h[0] = pull<S, AA, THERMAL, 0>(P, A, i, j);
+    h[1] = pull<S, AA, THERMAL, 1>(P, A, i, j);
+    h[2] = pull<S, AA, THERMAL, 2>(P, A, i, j);
+    h[3] = pull<S, AA, THERMAL, 3>(P, A, i, j);
+    h[4] = pull<S, AA, THERMAL, 4>(P, A, i, j);
+}
+
+template <class S, int MODE>
+__device__ __forceinline__ void scatter(const KParams &P, S *A, int i, int j, bool interior,
+                                        const float (&f)[9], const float (&g)[5],
+                                        const float (&h)[5]) {
+    const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+    if (MODE == MODE_AB) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Conv<S>::st(A + (long long)q * P.plane + n, f[q], skey(i, j, q));
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            Conv<S>::st(A + (long long)(GOFF + q) * P.plane + n, g[q], skey(i, j, GOFF + q));
+            Conv<S>::st(A + (long long)(HOFF + q) * P.plane + n, h[q], skey(i, j, HOFF + q));
+        }
+    } else if (MODE == MODE_AA_EVEN) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            Conv<S>::st(A + (long long)Lat<FLOW>::opp(q) * P.plane + n, f[q], skey(i, j, q));
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            Conv<S>::st(A + (long long)(GOFF + Lat<SWIRL>::opp(q)) * P.plane + n, g[q],
+                        skey(i, j, GOFF + q));
+            Conv<S>::st(A + (long long)(HOFF + Lat<THERMAL>::opp(q)) * P.plane + n, h[q],
+                        skey(i, j, HOFF + q));
+        }
+    } else if (interior) {
+        push_in<S, FLOW, 0>(P, A, n, i, j, f[0]);
+        push_in<S, FLOW, 1>(P, A, n, i, j, f[1]);
+        push_in<S, FLOW, 2>(P, A, n, i, j, f[2]);
+        push_in<S, FLOW, 3>(P, A, n, i, j, f[3]);
+        push_in<S, FLOW, 4>(P, A, n, i, j, f[4]);
+        push_in<S, FLOW, 5>(P, A, n, i, j, f[5]);
+        push_in<S, FLOW, 6>(P, A, n, i, j, f[6]);
+        push_in<S, FLOW, 7>(P, A, n, i, j, f[7]);
+        push_in<S, FLOW, 8>(P, A, n, i, j, f[8]);
+        push_in<S, SWIRL, 0>(P, A, n, i, j, g[0]);
+        push_in<S, SWIRL, 1>(P, A, n, i, j, g[1]);
+        push_in<S, SWIRL, 2>(P, A, n, i, j, g[2]);
+        push_in<S, SWIRL, 3>(P, A, n, i, j, g[3]);
+        push_in<S, SWIRL, 4>(P, A, n, i, j, g[4]);
+        push_in<S, THERMAL, 0>(P, A, n, i, j, h[0]);
+        push_in<S, THERMAL, 1>(P, A, n, i, j, h[1]);
+        push_in<S, THERMAL, 2>(P, A, n, i, j, h[2]);
+        push_in<S, THERMAL, 3>(P, A, n, i, j, h[3]);
+        push_in<S, THERMAL, 4>(P, A, n, i, j, h[4]);
+    } else {
+        push<S, FLOW, 0>(P, A, i, j, f[0]);
+        push<S, FLOW, 1>(P, A, i, j, f[1]);
+        push<S, FLOW, 2>(P, A, i, j, f[2]);
+        push<S, FLOW, 3>(P, A, i, j, f[3]);
+        push<S, FLOW, 4>(P, A, i, j, f[4]);
+        push<S, FLOW, 5>(P, A, i, j, f[5]);
+        push<S, FLOW, 6>(P, A, i, j, f[6]);
+        push<S, FLOW, 7>(P, A, i, j, f[7]);
+        push<S, FLOW, 8>(P, A, i, j, f[8]);
+        push<S, SWIRL, 0>(P, A, i, j, g[0]);
+        push<S, SWIRL, 1>(P, A, i, j, g[1]);
+        push<S, SWIRL, 2>(P, A, i, j, g[2]);
+        push<S, SWIRL, 3>(P, A, i, j, g[3]);
+        push<S, SWIRL, 4>(P, A, i, j, g[4]);
+        push<S, THERMAL, 0>(P, A, i, j, h[0]);
+        push<S, THERMAL, 1>(P, A, i, j, h[1]);
+        push<S, THERMAL, 2>(P, A, i, j, h[2]);
+        push<S, THERMAL, 3>(P, A, i, j, h[3]);
+        push<S, THERMAL, 4>(P, A, i, j, h[4]);
+    }
+}
+
+// A node whose eight neighbours are all fluid nodes: no boundary rule can
+// apply to any of its links or derivative stencils.
+__device__ __forceinline__ bool interior_node(const KParams &P, int i, int j) {
+    return (unsigned)(i - 1) < (unsigned)(P.Nz - 2) && (unsigned)(j - 1) < (unsigned)(P.Nr - 2);
+}
+
+// One time step of node (i, j): stream (gather), output moments, half
+// source step, cascaded collisions with the source moments, store; the
+// node's half-step fields go to the lagged buffer of the next step.
+template <class S, int MODE>
+__device__ __forceinline__ void update_node(const KParams &P, const S *src, S *dst,
+                                            const float *__restrict__ Mprev,
+                                            float *__restrict__ Mnext, int i, int j) {
+    const bool interior = interior_node(P, i, j);
+    float f[9], g[5], h[5];
+    gather<S, MODE>(P, src, i, j, interior, f, g, h);
+    const Moments m = moments(f, g, h);
+    float d[5];
+    derivatives(P, Mprev, i, j, interior, d);
+    const float iy = rcp(P.r0 + (float)j + 0.5f);
+    const Half H = half_step(P, iy, m.drho, m.jx, m.jy, m.psi, m.dphi, d);
+    collide_f(P, f, H);
+    collide_adv(g, H.ux, H.uy, H.psi, H.psi, H.hSpsi, P.og12, P.og3, P.og4);
+    collide_adv(h, H.ux, H.uy, P.Tref + H.dphi, H.dphi, H.hSphi, P.oh12, P.oh3, P.oh4);
+    scatter<S, MODE>(P, dst, i, j, interior, f, g, h);
+    const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+    Mnext[n] = H.ux;
+    Mnext[P.plane + n] = H.uy;
+    Mnext[2 * P.plane + n] = H.psi * H.irho;
+    Mnext[3 * P.plane + n] = H.dphi;
+}
+
+}  // namespace axlb

@@ -1,0 +1,81 @@
+"""Batched stepping: uneven lattices in one fused launch per step must give
+every member exactly the result it gets alone."""
+import numpy as np
+import pytest
+
+from conftest import say
+from paper_1806_10241_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def members():
+    cases = [I.annulus_convection(Nr=48 + 17 * k, Nz=50 + 23 * k, Ra=10 ** (3 + 0.5 * k),
+                                  radius_ratio=1.5 + 0.5 * k, seed=40 + k) for k in range(4)]
+    cases.append(I.rotating_lid_cylinder(Nr=37, Nz=61, Re=300.0, Ri=0.3, seed=45))
+    cases.append(I.couette_poiseuille_conduction(Nr=30, Nz=8))
+    return cases
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_batch_equals_alone(gpu, storage):
+    say("batch vs alone", storage)
+    from paper_1806_10241_amd import axlb
+    cases = members()
+    alone = [axlb.Lattice(c, storage=storage) for c in cases]
+    batched = [axlb.Lattice(c, storage=storage) for c in cases]
+    # members may join with different phases
+    alone[1].step(1)
+    batched[1].step(1)
+    b = axlb.Batch(batched)
+    for tile, blocks in ((0, 0), (3, 0), (5, 2048), (7, 64)):
+        b.set_schedule(tile, blocks)
+        b.step(113)
+    b.sync()
+    for lat in alone:
+        lat.step(4 * 113)
+    for la, lb in zip(alone, batched):
+        assert lb.steps == la.steps
+        assert la.save() == lb.save()
+        fa, fb = la.fields(), lb.fields()
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k])
+    b.close()
+
+
+def test_batch_autotune_restores_state_and_members_are_locked(gpu):
+    say("batch autotune")
+    from paper_1806_10241_amd import axlb
+    cases = members()
+    a = [axlb.Lattice(c) for c in cases]
+    ref = [axlb.Lattice(c) for c in cases]
+    b = axlb.Batch(a)
+    tile, blocks, ms = b.autotune(steps_per_trial=4)
+    assert (tile, blocks) == b.schedule()
+    assert np.all(ms > 0)
+    lib = axlb.load()
+    assert lib.axlb_step(a[0].handle, 1) == axlb.ESTATE
+    assert lib.axlb_set_fields(a[0].handle, None, None, None, None, None) == axlb.ESTATE
+    b.step(150)
+    b.sync()
+    for lat in ref:
+        lat.step(150)
+    for x, y in zip(a, ref):
+        assert x.save() == y.save()
+    m, nodes = b.size()
+    assert m == len(cases) and nodes == sum(c["Nr"] * c["Nz"] for c in cases)
+    b.close()
+    a[0].step(1)  # released from the batch
+
+
+def test_step_each_matches_single_lattices(gpu):
+    say("step_each")
+    from paper_1806_10241_amd import axlb
+    cases = members()[:3]
+    a = [axlb.Lattice(c) for c in cases]
+    ref = [axlb.Lattice(c) for c in cases]
+    axlb.step_each(a, 37)
+    for lat in ref:
+        lat.step(37)
+    for x, y in zip(a, ref):
+        assert x.save() == y.save()
