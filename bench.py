@@ -28,6 +28,41 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_UPDATE = {"f32": 152, "f16": 76, "bf16": 76}
 
 
+STEP_SOURCES = ["paper_1806_10241_amd/csrc/axlb_node.h", "paper_1806_10241_amd/csrc/axlb_kernels.hip",
+                "paper_1806_10241_amd/csrc/axlb_device.h"]
+
+
+def step_kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in STEP_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(storage: str, Nr: int, Nz: int):
+    """HBM bytes per step-kernel launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); None
+    unless that summary was taken on the current step-kernel sources and on
+    this workload."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_%dx%d_%s.md" % (Nr, Nz, storage))
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != step_kernel_hash():
+        return None
+    try:
+        return int(float(vals["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(case, steps: int):
     """The FP64 oracle, single-threaded, on the first `steps` steps of the
     same workload; MLUPS over the stepping only."""
@@ -60,8 +95,13 @@ def bench_batched(n, steps, warmup, baseline_steps):
     b.step(steps)
     b.sync()
     dt = time.perf_counter() - t0
-    finite = all(np.isfinite(lat.residual()) for lat in lats[:4])
     b.close()
+    nonfinite = 0
+    for lat in lats:
+        try:
+            lat.residual()
+        except axlb.AxlbError:
+            nonfinite += 1
     axlb.step_each(lats, 2)
     for lat in lats:
         lat.sync()
@@ -79,7 +119,7 @@ def bench_batched(n, steps, warmup, baseline_steps):
             "solve": "1e4 steps of one instance",
             "schedule": {"tile": "%dx%d" % axlb.tile_shape(tile), "blocks": blocks},
             "loop_of_single_launches": {"steps": baseline_steps, "mlups": round(mlups_loop, 1)},
-            "speedup_vs_loop": round(mlups / mlups_loop, 2), "finite": bool(finite)}
+            "speedup_vs_loop": round(mlups / mlups_loop, 2), "nonfinite_instances": nonfinite}
 
 
 def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2):
@@ -255,7 +295,7 @@ def main():
                    "tile": "%dx%d" % tile_rz, "autotune_us_per_step": tune},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic(args.storage, args.Nr, args.Nz)},
         "finite": bool(r == r),
     }
     lat.close()

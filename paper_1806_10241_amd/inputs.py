@@ -74,11 +74,12 @@ def _axis(bc):
 
 
 def convection_velocity_scale_params(L: float, Pr: float, Ra: float, U: float = 0.05,
-                                     floor: float = 1.0 / 300.0):
+                                     floor: float = 0.01):
     """nu, alpha for a buoyancy velocity scale sqrt(g beta dT L) = U (kept
     small, Section 3.2): nu = U L sqrt(Pr/Ra), alpha = nu/Pr.  Coefficients
-    are floored at `floor` (relaxation time 0.51); the effective Ra is then
-    recomputed from g beta = U^2/L and returned."""
+    are floored at `floor` (relaxation time 0.53: below it the cell Reynolds
+    number U/nu of the under-resolved corners exceeds 5 and runs blow up);
+    the effective Ra is then recomputed from g beta = U^2/L and returned."""
     nu = U * L * math.sqrt(Pr / Ra)
     alpha = nu / Pr
     if nu < floor or alpha < floor:
