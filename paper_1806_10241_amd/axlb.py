@@ -88,6 +88,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libaxlb.so is not built (run __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname as the system's:
+    # loading torch first makes the library bind to that one, so that one
+    # runtime owns the device, its memory and its streams in this process.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     sig = {
         "axlb_state_bytes": ([C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_size_t)], C.c_int),

@@ -29,7 +29,7 @@ Layout layout_for(int Nr, int Nz, int storage, int layout) {
     const size_t a = 256;
     auto up = [&](size_t b) { return (b + a - 1) / a * a; };
     L.pop_bytes = up((size_t)NPOP * L.plane * storage_size(storage));
-    L.lag_bytes = up((size_t)NLAG * L.plane * sizeof(float));
+    L.lag_bytes = up(LAG_NODE_BYTES * L.plane);
     const size_t N = (size_t)Nr * Nz;
     L.fld_bytes = up(5 * N * sizeof(double));
     L.snap_bytes = up(4 * N * sizeof(double));
@@ -123,7 +123,7 @@ static int check_bcs(axlb_lattice *L) {
 static int launch_one(axlb_lattice *L, long t) {
     const KParams &P = L->P;
     const int par = (int)(t & 1);
-    float *Mprev = L->lag[par], *Mnext = L->lag[par ^ 1];
+    LagT *Mprev = L->lag[par], *Mnext = L->lag[par ^ 1];
     hipError_t e;
     if (L->layout == AXLB_LAYOUT_AA)
         e = launch_step(P, L->storage, L->tile, par == 0 ? 1 : 2, L->pop[0], L->pop[0], Mprev,
@@ -303,9 +303,9 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     } else {
         L->pop[1] = L->pop[0];
     }
-    L->lag[0] = (float *)p;
+    L->lag[0] = (LagT *)p;
     p += L->lay.lag_bytes;
-    L->lag[1] = (float *)p;
+    L->lag[1] = (LagT *)p;
     p += L->lay.lag_bytes;
     L->fld = (double *)p;
     p += L->lay.fld_bytes;

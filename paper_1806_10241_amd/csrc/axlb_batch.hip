@@ -22,7 +22,7 @@ namespace axlb {
 struct InstDesc {
     KParams P;
     void *pop;
-    float *lag[2];
+    LagT *lag[2];
     int parity0;     // member step count at batch creation, mod 2
     int tile_begin;  // first work-list entry of this member
     int gx;          // tiles along r

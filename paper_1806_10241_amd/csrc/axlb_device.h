@@ -17,8 +17,36 @@ enum { NOSLIP = 0, PERIODIC = 1, MIRROR = 2, DIRICHLET = 3, OMEGA_R = 4, ADIABAT
 constexpr int NPOP = 19;
 constexpr int GOFF = 9;
 constexpr int HOFF = 14;
-// Lagged derivative fields: u_x, u_y, u_theta, T - T_ref.
+// Lagged derivative fields, one block per time level: planes 0..2 hold
+// u_x, u_y, u_theta in binary16 scaled by 2^10 (values down to ~6e-8 stay
+// clear of subnormals, |values| up to 64 fit), plane 3 holds T - T_ref in
+// FP32.  They are rewritten every step, so their rounding never
+// accumulates, and they only enter the central differences of the
+// geometric sources.  Temperature keeps FP32: its gradient at the walls is
+// the Nusselt number, and binary16 (relative step 2^-11 on values up to
+// 1/2) would bias it at steady state.
 constexpr int NLAG = 4;
+using LagT = __half;
+constexpr float LAG_SCALE = 1024.f;
+constexpr size_t LAG_NODE_BYTES = 3 * sizeof(__half) + sizeof(float);
+__device__ __forceinline__ const float *lag_T(const LagT *M, long long plane) {
+    return reinterpret_cast<const float *>(M + 3 * plane);
+}
+__device__ __forceinline__ float *lag_T(LagT *M, long long plane) {
+    return reinterpret_cast<float *>(M + 3 * plane);
+}
+__device__ __forceinline__ float lag_h(const LagT *p) { return __half2float(*p) * (1.f / LAG_SCALE); }
+// Field v at element offset off of a block with the given plane size.
+template <class I>
+__device__ __forceinline__ float lag_ld(const LagT *M, int v, long long plane, I off) {
+    if (v == 3) return lag_T(M, plane)[off];
+    return lag_h(M + v * plane + off);
+}
+template <class I>
+__device__ __forceinline__ void lag_st(LagT *M, int v, long long plane, I off, float x) {
+    if (v == 3) lag_T(M, plane)[off] = x;
+    else M[v * plane + off] = __float2half_rn(x * LAG_SCALE);
+}
 
 // Everything a step kernel needs, passed by value.
 struct KParams {

@@ -38,7 +38,7 @@ struct axlb_lattice {
     axlb::Layout lay{};
     char *base = nullptr;
     void *pop[2] = {nullptr, nullptr};
-    float *lag[2] = {nullptr, nullptr};
+    axlb::LagT *lag[2] = {nullptr, nullptr};
     double *fld = nullptr, *snap = nullptr, *red = nullptr;
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     bool use_graphs = true;

@@ -5,8 +5,9 @@
 // Data layout in HBM (structure of arrays, r fastest, rows padded to
 // `pitch`): 19 population planes pop[q][iz][ir] holding shifted populations
 // f - w_q (rho_0 = 1), g, and h - w_q T_ref, in FP32, binary16 or bfloat16,
-// and 2 x 4 FP32 planes of the lagged derivative fields.  All arithmetic is
-// FP32; reductions are FP64.
+// and two blocks (time levels) of lagged derivative fields, each three
+// binary16 velocity planes and one FP32 temperature plane.  All arithmetic
+// is FP32; reductions are FP64.
 //
 // Streaming layouts:
 //  * AA (one buffer, in place).  Even phase: node n reads its own slots
@@ -25,8 +26,8 @@ namespace axlb {
 // One time step for every node of one lattice.
 template <class S, int MODE, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const S *src, S *dst,
-                                                   const float *__restrict__ Mprev,
-                                                   float *__restrict__ Mnext) {
+                                                   const LagT *__restrict__ Mprev,
+                                                   LagT *__restrict__ Mnext) {
     int i, j;
     tile_of<BX, BY>(P, i, j);
     if (i >= P.Nz || j >= P.Nr) return;
@@ -37,7 +38,7 @@ __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const S *src,
 // out = [rho, u_r, u_z, u_theta, T] planes of Nz*Nr doubles.
 template <class S, int MODE>
 __global__ void __launch_bounds__(TX * TY) k_fields(const KParams P, const S *src,
-                                                     const float *__restrict__ Mprev,
+                                                     const LagT *__restrict__ Mprev,
                                                      double *__restrict__ out) {
     int i, j;
     tile_of<TX, TY>(P, i, j);
@@ -71,7 +72,7 @@ __device__ __forceinline__ double w1(int e, double u) {
 
 template <class S, bool AA>
 __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
-                                                   const double *__restrict__ in, float *M) {
+                                                   const double *__restrict__ in, LagT *M) {
     int i, j;
     tile_of<TX, TY>(P, i, j);
     if (i >= P.Nz || j >= P.Nr) return;
@@ -108,10 +109,10 @@ __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
         Conv<S>::st(A + (HOFF + slot) * P.plane + n, (float)(he[q] - w * Tref),
                     skey(i, j, HOFF + q));
     }
-    M[n] = (float)uz;
-    M[P.plane + n] = (float)ur;
-    M[2 * P.plane + n] = (float)uth;
-    M[3 * P.plane + n] = (float)(T - Tref);
+    lag_st(M, 0, P.plane, n, (float)uz);
+    lag_st(M, 1, P.plane, n, (float)ur);
+    lag_st(M, 2, P.plane, n, (float)uth);
+    lag_st(M, 3, P.plane, n, (float)(T - Tref));
 }
 
 // ----------------------------------------------------------------------------
@@ -226,8 +227,8 @@ static dim3 step_grid(const KParams &P) { return grid_for(P, TX, TY); }
     X(5, 64, 1) X(6, 128, 4) X(7, 32, 8)
 
 template <class S, int BX, int BY>
-static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const float *Mprev,
-                             float *Mnext, hipStream_t st) {
+static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT *Mprev,
+                             LagT *Mnext, hipStream_t st) {
     const dim3 grid = grid_for(P, BX, BY), block(BX * BY);
     switch (mode) {
     case MODE_AB: k_step<S, MODE_AB, BX, BY><<<grid, block, 0, st>>>(P, a, b, Mprev, Mnext); break;
@@ -238,7 +239,7 @@ static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const float
 
 template <class S>
 static hipError_t launch_step_t(const KParams &P, int tile, int mode, void *src, void *dst,
-                                const float *Mprev, float *Mnext, hipStream_t st) {
+                                const LagT *Mprev, LagT *Mnext, hipStream_t st) {
     S *a = (S *)src, *b = (S *)dst;
     switch (tile) {
 #define AXLB_CASE(id, bx, by) \
@@ -251,7 +252,7 @@ static hipError_t launch_step_t(const KParams &P, int tile, int mode, void *src,
 }
 
 template <class S>
-static hipError_t launch_fields_t(const KParams &P, int mode, const void *src, const float *Mprev,
+static hipError_t launch_fields_t(const KParams &P, int mode, const void *src, const LagT *Mprev,
                                   double *out, hipStream_t st) {
     const dim3 grid = step_grid(P), block(TX * TY);
     const S *a = (const S *)src;
@@ -264,7 +265,7 @@ static hipError_t launch_fields_t(const KParams &P, int mode, const void *src, c
 }
 
 template <class S>
-static hipError_t launch_init_t(const KParams &P, bool aa, void *pop, const double *in, float *M,
+static hipError_t launch_init_t(const KParams &P, bool aa, void *pop, const double *in, LagT *M,
                                 hipStream_t st) {
     const dim3 grid = step_grid(P), block(TX * TY);
     if (aa) k_init<S, true><<<grid, block, 0, st>>>(P, (S *)pop, in, M);
@@ -273,7 +274,7 @@ static hipError_t launch_init_t(const KParams &P, bool aa, void *pop, const doub
 }
 
 hipError_t launch_step(const KParams &P, int storage, int tile, int mode, void *src, void *dst,
-                       const float *Mprev, float *Mnext, hipStream_t st) {
+                       const LagT *Mprev, LagT *Mnext, hipStream_t st) {
     if (storage == STORE_F16)
         return launch_step_t<__half>(P, tile, mode, src, dst, Mprev, Mnext, st);
     if (storage == STORE_BF16)
@@ -294,14 +295,14 @@ void tile_shape(int tile, int *bx, int *by) {
 }
 
 hipError_t launch_fields(const KParams &P, int storage, int mode, const void *src,
-                         const float *Mprev, double *out, hipStream_t st) {
+                         const LagT *Mprev, double *out, hipStream_t st) {
     if (storage == STORE_F16) return launch_fields_t<__half>(P, mode, src, Mprev, out, st);
     if (storage == STORE_BF16) return launch_fields_t<__hip_bfloat16>(P, mode, src, Mprev, out, st);
     return launch_fields_t<float>(P, mode, src, Mprev, out, st);
 }
 
 hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
-                       float *M, hipStream_t st) {
+                       LagT *M, hipStream_t st) {
     if (storage == STORE_F16) return launch_init_t<__half>(P, aa, pop, in, M, st);
     if (storage == STORE_BF16) return launch_init_t<__hip_bfloat16>(P, aa, pop, in, M, st);
     return launch_init_t<float>(P, aa, pop, in, M, st);

@@ -17,11 +17,11 @@ void tile_shape(int tile, int *bx, int *by);
 
 // mode: 0 = AB pull (src -> dst), 1 = AA odd phase, 2 = AA even phase (src == dst).
 hipError_t launch_step(const KParams &P, int storage, int tile, int mode, void *src, void *dst,
-                       const float *Mprev, float *Mnext, hipStream_t st);
+                       const LagT *Mprev, LagT *Mnext, hipStream_t st);
 hipError_t launch_fields(const KParams &P, int storage, int mode, const void *src,
-                         const float *Mprev, double *out, hipStream_t st);
+                         const LagT *Mprev, double *out, hipStream_t st);
 hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
-                       float *M, hipStream_t st);
+                       LagT *M, hipStream_t st);
 hipError_t launch_residual(const double *fld, const double *snap, long long N, double *part,
                            int nblocks, double *out9, hipStream_t st);
 hipError_t launch_nusselt(const double *T, int Nr, int Nz, int cylinder, double r0, double Ta,

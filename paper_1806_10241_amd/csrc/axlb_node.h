@@ -168,16 +168,16 @@ __device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float
 // through the half-way wall: -q for u_x, u_y at a no-slip wall, 2 q_w - q
 // for an imposed u_theta or T, q for zero flux; q (u_x, T) or -q (u_y,
 // u_theta) at the axis; the wrapped node on a periodic face.
-__device__ __forceinline__ float lag_edge(const KParams &P, const float *M, int v, int i, int j,
-                                       int di, int dj) {
+__device__ __forceinline__ float lag_edge(const KParams &P, const LagT *M, int v, int i, int j,
+                                          int di, int dj) {
     const int ni = i + di, nj = j + dj;
-    const float q1 = M[v * P.plane + (long long)i * P.pitch + j];
+    const float q1 = lag_ld(M, v, P.plane, (long long)i * P.pitch + j);
     const int face = nj < 0 ? R_IN : (nj >= P.Nr ? R_OUT : (ni < 0 ? Z_LO : Z_HI));
     const int fld = v <= 1 ? FLOW : (v == 2 ? SWIRL : THERMAL);
     const int k = kind_of(P, face, fld);
     if (k == PERIODIC) {
         const int wi = ni < 0 ? ni + P.Nz : ni - P.Nz;
-        return M[v * P.plane + (long long)wi * P.pitch + nj];
+        return lag_ld(M, v, P.plane, (long long)wi * P.pitch + nj);
     }
     if (k == MIRROR) return (v == 0 || v == 3) ? q1 : -q1;
     if (k == ADIABATIC) return q1;
@@ -187,11 +187,11 @@ __device__ __forceinline__ float lag_edge(const KParams &P, const float *M, int 
     return 2.f * s - q1;
 }
 
-__device__ __forceinline__ float lag(const KParams &P, const float *M, int v, int i, int j, int di,
+__device__ __forceinline__ float lag(const KParams &P, const LagT *M, int v, int i, int j, int di,
                                      int dj) {
     const int ni = i + di, nj = j + dj;
     if ((unsigned)ni < (unsigned)P.Nz && (unsigned)nj < (unsigned)P.Nr)
-        return M[v * P.plane + (long long)ni * P.pitch + nj];
+        return lag_ld(M, v, P.plane, (long long)ni * P.pitch + nj);
     return lag_edge(P, M, v, i, j, di, dj);
 }
 
@@ -342,16 +342,17 @@ __device__ __forceinline__ Moments moments(const float (&f)[9], const float (&g)
     return m;
 }
 
-__device__ __forceinline__ void derivatives(const KParams &P, const float *M, int i, int j,
+__device__ __forceinline__ void derivatives(const KParams &P, const LagT *M, int i, int j,
                                             bool interior, float d[5]) {
     if (interior) {
         // all four neighbours are fluid nodes: plain loads at 32-bit offsets
         const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j, w = (unsigned)P.pitch;
-        const float *Mx = M, *My = M + P.plane, *Mt = M + 2 * P.plane, *Mp = M + 3 * P.plane;
-        d[0] = 0.5f * (My[n + w] - My[n - w]);
-        d[1] = 0.5f * (Mx[n + 1] - Mx[n - 1]);
-        d[2] = 0.5f * (My[n + 1] - My[n - 1]);
-        d[3] = 0.5f * (Mt[n + 1] - Mt[n - 1]);
+        const LagT *Mx = M, *My = M + P.plane, *Mt = M + 2 * P.plane;
+        const float *Mp = lag_T(M, P.plane);
+        d[0] = 0.5f * (lag_h(My + (n + w)) - lag_h(My + (n - w)));
+        d[1] = 0.5f * (lag_h(Mx + (n + 1)) - lag_h(Mx + (n - 1)));
+        d[2] = 0.5f * (lag_h(My + (n + 1)) - lag_h(My + (n - 1)));
+        d[3] = 0.5f * (lag_h(Mt + (n + 1)) - lag_h(Mt + (n - 1)));
         d[4] = 0.5f * (Mp[n + 1] - Mp[n - 1]);
         return;
     }
@@ -539,8 +540,8 @@ __device__ __forceinline__ bool interior_node(const KParams &P, int i, int j) {
 // node's half-step fields go to the lagged buffer of the next step.
 template <class S, int MODE>
 __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *dst,
-                                            const float *__restrict__ Mprev,
-                                            float *__restrict__ Mnext, int i, int j) {
+                                            const LagT *__restrict__ Mprev,
+                                            LagT *__restrict__ Mnext, int i, int j) {
     const bool interior = interior_node(P, i, j);
     float f[9], g[5], h[5];
     gather<S, MODE>(P, src, i, j, interior, f, g, h);
@@ -554,10 +555,10 @@ __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *d
     collide_adv(h, H.ux, H.uy, P.Tref + H.dphi, H.dphi, H.hSphi, P.oh12, P.oh3, P.oh4);
     scatter<S, MODE>(P, dst, i, j, interior, f, g, h);
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
-    Mnext[n] = H.ux;
-    Mnext[P.plane + n] = H.uy;
-    Mnext[2 * P.plane + n] = H.psi * H.irho;
-    Mnext[3 * P.plane + n] = H.dphi;
+    lag_st(Mnext, 0, P.plane, n, H.ux);
+    lag_st(Mnext, 1, P.plane, n, H.uy);
+    lag_st(Mnext, 2, P.plane, n, H.psi * H.irho);
+    lag_st(Mnext, 3, P.plane, n, H.dphi);
 }
 
 }  // namespace axlb

@@ -162,6 +162,54 @@ def rotating_lid_cylinder(Nr: int = 1024, Nz: int = 2048, Re: float = 1000.0,
                 fields=_perturbed_T(seed, Nz, Nr))
 
 
+def rayleigh_benard_cylinder(Nr: int = 100, Nz: int = 100, Pr: float = 0.7, Ra: float = 5e3,
+                             T_init: float = 0.0, seed: int = 6, U: float = 0.05) -> dict:
+    """Rayleigh-Benard convection in a closed vertical cylinder (Section 3.3):
+    hot bottom lid T = 1, cold top lid T = 0, adiabatic no-slip side wall,
+    axis by the mirror rule, gravity along -z.  R = Nr, H = Nz, Ra uses
+    L = H and the free-fall velocity sqrt(g beta dT H) = U.  The fluid starts
+    at rest at T_init (0: the cold start, 1: the hot start) plus seeded
+    noise of amplitude 1e-4."""
+    nu, alpha, Ra_eff = convection_velocity_scale_params(Nz, Pr, Ra, U)
+    bc = {}
+    _axis(bc)
+    _walls(bc, R_OUT)
+    _walls(bc, Z_LO, thermal=(DIRICHLET, 1.0))
+    _walls(bc, Z_HI, thermal=(DIRICHLET, 0.0))
+    # Ra is defined with H here: g beta = U^2 / H, expressed in the
+    # library's convention Ra_lib = g beta Nr^3 / (nu alpha)
+    gbeta = U * U / Nz
+    return dict(name="rayleigh_benard_cylinder", Nr=Nr, Nz=Nz, cylinder=1, r_inner=0.0,
+                nu=nu, alpha=alpha, Pr=nu / alpha, Ra=gbeta * Nr ** 3 / (nu * alpha),
+                Ra_H=Ra_eff, U_ff=U, g_axial=0.0, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5,
+                seed=seed, fields=_perturbed_T(seed, Nz, Nr, base=T_init))
+
+
+def mixed_convection_annulus(Nr: int = 40, slenderness: float = 10.0, Re: float = 100.0,
+                             sigma: float = 0.0, Pr: float = 0.7, u_wall: float = 0.05,
+                             seed: int = 7) -> dict:
+    """Mixed convection in a slender annulus with a rotating inner cylinder
+    (Section 3.5): D = R_o - R_i = Nr, R_o/R_i = 2, H = slenderness * D,
+    inner wall u_theta = Omega_i R_i = u_wall and T = 1, outer wall at rest
+    and T = 0, adiabatic no-slip lids, gravity along -z.  Re = u_wall D/nu,
+    Gr = g beta dT D^3/nu^2 = sigma Re^2, Pr = nu/alpha.  Starts at rest at
+    T = 0.5 plus seeded noise of amplitude 1e-4."""
+    D = float(Nr)
+    Nz = int(round(slenderness * Nr))
+    nu = u_wall * D / Re
+    alpha = nu / Pr
+    gbeta = sigma * u_wall * u_wall / D
+    bc = {}
+    _walls(bc, R_IN, (DIRICHLET, u_wall), (DIRICHLET, 1.0))
+    _walls(bc, R_OUT, (NOSLIP, 0.0), (DIRICHLET, 0.0))
+    _walls(bc, Z_LO)
+    _walls(bc, Z_HI)
+    return dict(name="mixed_convection_annulus", Nr=Nr, Nz=Nz, cylinder=0, r_inner=D,
+                nu=nu, alpha=alpha, Pr=Pr, Ra=gbeta * D ** 3 / (nu * alpha), Re=Re,
+                sigma=sigma, g_axial=0.0, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5, seed=seed,
+                fields=_perturbed_T(seed, Nz, Nr))
+
+
 def batched_annuli(n: int = 256, seed: int = 4):
     """Uneven annulus convection instances: Nr ~ U{48..256}, Nz ~ U{48..512},
     Ra log-uniform in [1e3, 1e6], Pr log-uniform in [0.02, 7], radius ratio

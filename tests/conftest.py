@@ -35,3 +35,16 @@ def gpu():
 def say(*a):
     """Progress line that names the GPU case about to run."""
     print(*a, flush=True)
+
+
+def golden(name):
+    """Rows of a fixture under tests/golden/ (values the paper prints; the
+    file header cites the table): list of tuples of str."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    rows = []
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append(tuple(line.split()))
+    return rows

@@ -1,25 +1,33 @@
-"""Steady states on the GPU: natural convection in a vertical annulus against
-the paper's Table 1 (a loose band: the paper's aspect ratio is ambiguous,
-2 in the text of Section 3.2 and 1 in this workload), and the steady wall
-Nusselt numbers against the oracle (within 0.5%)."""
+"""Steady states on the GPU against the values the paper prints for its
+validation problems, on the paper's grids or finer, and the steady wall
+Nusselt numbers against the oracle (within 0.5%):
+
+* Table 1 (Section 3.2): mean Nusselt number between coaxial cylinders,
+  Pr = 0.7, R_o/R_i = 2, H/L = 2, at 128 x 256 nodes;
+* Table 2 (Section 3.3): maximum speed of Rayleigh-Benard convection in a
+  cylinder (axis condition), Ra = 5e3, Pr = 0.7, H/R = 1, at 100 x 100;
+* Table 3 (Section 3.5): equivalent conductivity of mixed convection with a
+  rotating inner cylinder, Re = 100, Pr = 0.7, H/D = 10, at 40 x 400."""
 import math
 
+import numpy as np
 import pytest
 
-from conftest import say
+from conftest import golden, say
 from paper_1806_10241_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-# Table 1, cascaded-LB column: mean Nusselt number at Pr = 0.7, R_o/R_i = 2
-TABLE1 = {1e3: 1.688, 1e4: 3.211, 1e5: 5.781}
+TABLE1 = {float(ra): float(nu) for ra, nu in golden("table1_annulus_nusselt.txt")}
+TABLE2 = {p: float(v) for p, v in golden("table2_rb_cylinder_max_velocity.txt")}
+TABLE3 = {float(s): float(k) for s, k in golden("table3_mixed_convection_keq.txt")}
 
 
-def run_to_steady(lat, tol=1e-8, max_steps=600_000):
+def run_to_steady(lat, tol=1e-9, chunk=5000, max_steps=2_000_000):
     lat.residual()
     r = math.inf
     while lat.steps < max_steps:
-        lat.step(5000)
+        lat.step(chunk)
         r = lat.residual()
         if r < tol:
             break
@@ -27,18 +35,61 @@ def run_to_steady(lat, tol=1e-8, max_steps=600_000):
 
 
 @pytest.mark.parametrize("Ra", [1e3, 1e4, 1e5])
-def test_annulus_nusselt_against_table1(gpu, Ra):
-    say("table 1 band, Ra", Ra)
+def test_table1_mean_nusselt(gpu, Ra):
+    say("table 1, Ra", Ra)
     from paper_1806_10241_amd import axlb
-    c = I.annulus_convection(Nr=128, Nz=128, Pr=0.7, Ra=Ra)
+    c = I.annulus_convection(Nr=128, Nz=256, Pr=0.7, Ra=Ra)
     lat = axlb.Lattice(c)
-    r = run_to_steady(lat, tol=1e-9)
+    r = run_to_steady(lat)
     nu_i, nu_o, mean = lat.nusselt()
-    say("  steps %d residual %.2e Nu_i %.4f Nu_o %.4f mean %.4f (table %.3f)"
-        % (lat.steps, r, nu_i, nu_o, mean, TABLE1[Ra]))
-    assert r < 1e-8
-    assert abs(nu_i - nu_o) < 0.02 * mean           # energy balance at steady state
-    assert abs(mean - TABLE1[Ra]) < 0.05 * TABLE1[Ra]
+    say("  steps %d residual %.2e Nu_i %.4f Nu_o %.4f mean %.4f (table %.3f, %+.2f%%)"
+        % (lat.steps, r, nu_i, nu_o, mean, TABLE1[Ra], 100 * (mean / TABLE1[Ra] - 1)))
+    assert r < 1e-9
+    assert abs(nu_i - nu_o) < 0.01 * mean           # energy balance at steady state
+    assert abs(mean - TABLE1[Ra]) < 0.01 * TABLE1[Ra]
+
+
+@pytest.mark.parametrize("T_init", [0.0, 1.0])
+def test_table2_rayleigh_benard_max_speed(gpu, T_init):
+    say("table 2, start T =", T_init)
+    from paper_1806_10241_amd import axlb
+    N = 100
+    c = I.rayleigh_benard_cylinder(Nr=N, Nz=N, T_init=T_init)
+    lat = axlb.Lattice(c)
+    r = run_to_steady(lat)
+    F = lat.fields()
+    speed = np.sqrt(F["uz"] ** 2 + F["ur"] ** 2)
+    m = float(speed.max()) / c["U_ff"]
+    axis = F["uz"][N // 2, 0] / c["U_ff"]
+    pattern = "up" if axis > 0 else "down"
+    say("  steps %d residual %.2e max speed %.4f, %s-flow (axis u_z %+.4f), table %.3f"
+        % (lat.steps, r, m, pattern, axis, TABLE2[pattern]))
+    assert r < 1e-9 and abs(axis) > 0.2
+    assert abs(m - TABLE2[pattern]) < 0.01 * TABLE2[pattern]
+
+
+def cell_count(ur_mid_gap):
+    """Taylor cells along z: u_r at mid-gap changes sign once inside each
+    cell, between the outflow and the inflow boundary of the cell."""
+    s = np.sign(ur_mid_gap[np.abs(ur_mid_gap) > 1e-9])
+    return int(np.count_nonzero(s[1:] != s[:-1]))
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.01, 0.05])
+def test_table3_equivalent_conductivity(gpu, sigma):
+    say("table 3, sigma", sigma)
+    from paper_1806_10241_amd import axlb
+    c = I.mixed_convection_annulus(Nr=40, slenderness=10.0, Re=100.0, sigma=sigma)
+    lat = axlb.Lattice(c)
+    r = run_to_steady(lat, max_steps=4_000_000)
+    nu_i, nu_o, _ = lat.nusselt()
+    keq = nu_i * math.log(2.0)
+    F = lat.fields()
+    cells = cell_count(F["ur"][:, c["Nr"] // 2])
+    say("  steps %d residual %.2e k_eq %.4f (table %.3f, %+.2f%%), Nu_o %.4f, %d cells"
+        % (lat.steps, r, keq, TABLE3[sigma], 100 * (keq / TABLE3[sigma] - 1), nu_o, cells))
+    assert r < 1e-9
+    assert abs(keq - TABLE3[sigma]) < 0.02 * TABLE3[sigma]
 
 
 def test_steady_nusselt_matches_oracle(gpu, orc):

@@ -113,6 +113,54 @@ def test_nusselt_conduction(c1_runs, refinement_runs):
     assert max(e[2]) < 0.015 * exact
 
 
+def couette_case(beta, Nr, kappa=0.1, Re=5.0, tau=0.6, Nz=4):
+    """Section 3.1: circular Couette flow between cylinders of radius ratio
+    beta = R_i/R_o, angular velocity ratio kappa = Omega_o/Omega_i,
+    Re = u_o R_i / nu with u_o = Omega_i R_i, tau = 0.6, periodic z."""
+    nu = (tau - 0.5) / 3.0
+    Ri = beta * Nr / (1.0 - beta)
+    u_o = Re * nu / Ri
+    bc = {}
+    I._walls(bc, I.R_IN, (I.DIRICHLET, u_o), (I.ADIABATIC, 0.0))
+    I._walls(bc, I.R_OUT, (I.DIRICHLET, kappa * u_o / beta), (I.ADIABATIC, 0.0))
+    I._periodic_z(bc)
+    return dict(Nr=Nr, Nz=Nz, cylinder=0, r_inner=Ri, nu=nu, alpha=nu, Ra=0.0, g_axial=0.0,
+                T0=0.5, bc=bc), Ri, Ri + Nr, u_o
+
+
+def couette_profile(beta, kappa, Ri, Ro, u_o, r):
+    """u_theta = A r + B / r (Section 3.1) with Omega_i = u_o/R_i and
+    Omega_o = kappa Omega_i."""
+    Oi = u_o / Ri
+    Oo = kappa * Oi
+    A = (Oo * Ro ** 2 - Oi * Ri ** 2) / (Ro ** 2 - Ri ** 2)
+    B = (Oi - Oo) * Ri ** 2 * Ro ** 2 / (Ro ** 2 - Ri ** 2)
+    return A * r + B / r
+
+
+def couette_error(orc, beta, Nr, steps):
+    c, Ri, Ro, u_o = couette_case(beta, Nr)
+    L = orc.Lattice(c, deriv_mode=2, fields={"T": np.full((c["Nz"], c["Nr"]), 0.5)})
+    L.step(steps)
+    r = Ri + np.arange(c["Nr"]) + 0.5
+    F = L.fields()
+    assert np.abs(F["uz"]).max() < 1e-12 and np.abs(F["ur"]).max() < 1e-8 * u_o
+    return rel_l2(F["uth"][0], couette_profile(beta, 0.1, Ri, Ro, u_o, r))
+
+
+@pytest.mark.parametrize("beta", [0.103, 0.203, 0.303, 0.503])
+def test_couette_radius_ratio_sweep(orc, beta):
+    """The radius-ratio sweep of Section 3.1 (kappa = 0.1, Re = 5,
+    tau = 0.6; Figure 1) on a coarser grid, R_o - R_i = 24 rows: within
+    1e-2 (rel. L2), and second order under refinement at the smallest
+    ratio, where the inner wall is 2.8 nodes from the axis."""
+    e24 = couette_error(orc, beta, 24, 40000)
+    assert e24 < 1e-2
+    if beta == 0.103:
+        e48 = couette_error(orc, beta, 48, 120000)
+        assert math.log2(e24 / e48) > 1.8
+
+
 def pipe_case(R=16, Nz=2, g=1e-6, Omega=5e-4, nu=0.1):
     bc = {}
     for fld in (I.FLOW, I.SWIRL, I.THERMAL):
