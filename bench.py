@@ -122,7 +122,7 @@ def bench_batched(n, steps, warmup, baseline_steps):
             "speedup_vs_loop": round(mlups / mlups_loop, 2), "nonfinite_instances": nonfinite}
 
 
-def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2):
+def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, order, window):
     """Poisson arrivals of mixed solve requests (seeded trace) served by the
     continuous-batching pool, against serving the same trace one request at
     a time with plain single-lattice runs.  Latency = arrival to result."""
@@ -131,7 +131,7 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2):
 
     trace = I.serving_trace(n=n, rate=rate, seed=5, max_nr_log2=max_nr_log2,
                             max_nz_log2=max_nz_log2)
-    pool = axlb.Pool(budget_bytes=int(budget_gib * (1 << 30)))
+    pool = axlb.Pool(budget_bytes=int(budget_gib * (1 << 30)), order=order, node_window=window)
     arrival, done, steps_of = {}, {}, {}
     pending = list(trace)
     t0 = time.perf_counter()
@@ -174,7 +174,7 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2):
     lat1 = np.array(lat1)
     makespan1 = finish
     return {"requests": n, "rate_per_s": rate, "tol": tol, "max_steps": max_steps,
-            "budget_gib": budget_gib,
+            "budget_gib": budget_gib, "admission": order, "node_window": window,
             "grid": "Nr 64..%d x Nz 64..%d" % (2 ** max_nr_log2, 2 ** max_nz_log2),
             "p50_s": round(float(np.percentile(lat_s, 50)), 4),
             "p99_s": round(float(np.percentile(lat_s, 99)), 4),
@@ -201,13 +201,16 @@ def main():
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10000)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--serve-n", type=int, default=48)
+    ap.add_argument("--serve-n", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-tol", type=float, default=1e-7)
-    ap.add_argument("--serve-max-steps", type=int, default=20000)
+    ap.add_argument("--serve-max-steps", type=int, default=100000)
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
-    ap.add_argument("--serve-max-nr-log2", type=float, default=8.0)
-    ap.add_argument("--serve-max-nz-log2", type=float, default=9.0)
+    ap.add_argument("--serve-max-nr-log2", type=float, default=10.0)
+    ap.add_argument("--serve-max-nz-log2", type=float, default=11.0)
+    ap.add_argument("--serve-order", default="smallest", choices=["smallest", "fifo"])
+    ap.add_argument("--serve-window", type=int, default=4 << 20,
+                    help="cap on resident fluid nodes in the pool (0: none)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--single-launches", action="store_true",
                     help="one kernel launch per step instead of 100-step graphs")
@@ -306,7 +309,8 @@ def main():
         print("bench: served, %d requests" % args.serve_n, file=sys.stderr, flush=True)
         out["served"] = bench_served(args.serve_n, args.serve_rate, args.serve_tol,
                                      args.serve_max_steps, args.serve_budget_gib,
-                                     args.serve_max_nr_log2, args.serve_max_nz_log2)
+                                     args.serve_max_nr_log2, args.serve_max_nz_log2,
+                                     args.serve_order, args.serve_window)
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -229,8 +229,9 @@ const char *axlb_batch_last_error(const axlb_batch *b);
 int axlb_step_each(axlb_lattice *const *lats, int n, long steps);
 
 /* ---- continuous-batching request pool ----
- * Solve requests (any size, parameters and storage) wait in a first-come
- * first-served queue and are admitted while their state fits a fixed
+ * Solve requests (any size, parameters and storage) wait in a queue and are
+ * admitted, in the pool's order (first come first served unless
+ * axlb_pool_set_policy says otherwise), while their state fits a fixed
  * device-memory budget (and at most max_members run at once).  Admitted
  * requests stay resident and advance together: each axlb_pool_tick runs one
  * 100-step bundle of every resident request as fused batched launches (one
@@ -262,6 +263,19 @@ typedef struct {
 } axlb_request;
 
 int axlb_pool_create(size_t budget_bytes, int device, int max_members, axlb_pool **out);
+/* Admission order and concurrency.  order: AXLB_POOL_FIFO (arrival order,
+ * the default) or AXLB_POOL_SMALLEST_FIRST (least Nr*Nz*max_steps first,
+ * ties in arrival order: shortest job first on the only work estimate known
+ * at admission; a steady stream of small requests can delay a large one
+ * indefinitely).  node_window > 0 caps the fluid nodes resident at once, so
+ * that the device stays busy without time-slicing every waiting request (a
+ * request larger than the window still runs when nothing else does); 0
+ * lifts the cap (the default).  In either order the request next in line
+ * that does not fit blocks those behind it.  Takes effect at the next tick.
+ * AXLB_EINVAL for an unknown order or a negative window. */
+#define AXLB_POOL_FIFO 0
+#define AXLB_POOL_SMALLEST_FIRST 1
+int axlb_pool_set_policy(axlb_pool *p, int order, long long node_window);
 /* Queues a request (copies it); *id identifies it.  AXLB_ENOMEM if its
  * state alone exceeds the budget. */
 int axlb_pool_submit(axlb_pool *p, const axlb_request *r, long *id);

@@ -37,10 +37,12 @@ EXPORTS = [
     "axlb_autotune", "axlb_batch_create", "axlb_batch_size", "axlb_batch_step",
     "axlb_batch_sync", "axlb_batch_set_schedule", "axlb_batch_get_schedule",
     "axlb_batch_autotune", "axlb_batch_destroy", "axlb_batch_last_error", "axlb_step_each",
-    "axlb_pool_create", "axlb_pool_submit", "axlb_pool_tick", "axlb_pool_status",
+    "axlb_pool_create", "axlb_pool_set_policy", "axlb_pool_submit", "axlb_pool_tick",
+    "axlb_pool_status",
     "axlb_pool_result", "axlb_pool_usage", "axlb_pool_destroy", "axlb_pool_last_error",
 ]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+POOL_ORDER = {"fifo": 0, "smallest": 1}
 NTILES = 8
 NSCHEDULES = 4
 
@@ -128,6 +130,7 @@ def load():
         "axlb_batch_last_error": ([_vp], C.c_char_p),
         "axlb_step_each": ([C.POINTER(_vp), C.c_int, C.c_long], C.c_int),
         "axlb_pool_create": ([C.c_size_t, C.c_int, C.c_int, C.POINTER(_vp)], C.c_int),
+        "axlb_pool_set_policy": ([_vp, C.c_int, C.c_longlong], C.c_int),
         "axlb_pool_submit": ([_vp, C.POINTER(Request), C.POINTER(C.c_long)], C.c_int),
         "axlb_pool_tick": ([_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "axlb_pool_status": ([_vp, C.c_long, C.POINTER(C.c_int), C.POINTER(C.c_long), _dp],
@@ -404,7 +407,8 @@ def make_request(case: dict, storage: str = "f32", tol: float = 1e-7,
 class Pool:
     """Continuous-batching request pool (``axlb_pool_*``)."""
 
-    def __init__(self, budget_bytes: int, device: int = 0, max_members: int = 4096):
+    def __init__(self, budget_bytes: int, device: int = 0, max_members: int = 4096,
+                 order: str = "fifo", node_window: int = 0):
         lib = load()
         self._lib = lib
         self._h = _vp()
@@ -413,6 +417,12 @@ class Pool:
         if rc:
             raise AxlbError(rc, lib.axlb_pool_last_error(None).decode())
         self.shapes = {}
+        self.set_policy(order, node_window)
+
+    def set_policy(self, order: str = "fifo", node_window: int = 0):
+        """order: "fifo" | "smallest" (least Nr*Nz*max_steps first);
+        node_window: cap on resident fluid nodes (0: none)."""
+        self._check(self._lib.axlb_pool_set_policy(self._h, POOL_ORDER[order], int(node_window)))
 
     def _check(self, rc):
         if rc:

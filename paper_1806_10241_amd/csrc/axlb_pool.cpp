@@ -39,6 +39,9 @@ struct Req {
 struct axlb_pool {
     size_t budget = 0, used = 0;
     int device = 0, max_members = 0;
+    int order = AXLB_POOL_FIFO;
+    long long node_window = 0;  // 0: no cap on resident nodes
+    long long nodes = 0;        // fluid nodes resident now
     long next_id = 1;
     std::deque<long> queue;
     std::map<long, Req> reqs;
@@ -143,6 +146,15 @@ int axlb_pool_create(size_t budget_bytes, int device, int max_members, axlb_pool
     return AXLB_OK;
 }
 
+int axlb_pool_set_policy(axlb_pool *p, int order, long long node_window) {
+    if (!p) return pfail(nullptr, AXLB_EINVAL, "pool is NULL");
+    if ((order != AXLB_POOL_FIFO && order != AXLB_POOL_SMALLEST_FIRST) || node_window < 0)
+        return pfail(p, AXLB_EINVAL, "bad pool policy");
+    p->order = order;
+    p->node_window = node_window;
+    return AXLB_OK;
+}
+
 int axlb_pool_submit(axlb_pool *p, const axlb_request *r, long *id) {
     if (!p || !r || !id) return pfail(p, AXLB_EINVAL, "NULL argument");
     size_t bytes = 0;
@@ -167,13 +179,31 @@ int axlb_pool_submit(axlb_pool *p, const axlb_request *r, long *id) {
 int axlb_pool_tick(axlb_pool *p, int *running, int *queued) {
     if (!p) return pfail(nullptr, AXLB_EINVAL, "pool is NULL");
     if (hipSetDevice(p->device) != hipSuccess) return pfail(p, AXLB_EDEVICE, "hipSetDevice failed");
-    // 1. admission, first come first served, while the budget allows
+    // 1. admission in the pool's order while the budget, the member limit
+    //    and the node window allow; the request next in order that does not
+    //    fit blocks the ones behind it
     int members = 0;
     for (auto &kv : p->reqs) members += kv.second.state == AXLB_REQ_RUNNING;
     while (!p->queue.empty()) {
-        Req &q = p->reqs[p->queue.front()];
+        auto next = p->queue.begin();
+        if (p->order == AXLB_POOL_SMALLEST_FIRST) {
+            // least nodes x max_steps; the queue is in arrival order, so the
+            // first minimum breaks ties by arrival
+            double best = INFINITY;
+            for (auto it = p->queue.begin(); it != p->queue.end(); ++it) {
+                const axlb_request &r = p->reqs[*it].r;
+                const double work = (double)r.Nr * r.Nz * (double)r.max_steps;
+                if (work < best) {
+                    best = work;
+                    next = it;
+                }
+            }
+        }
+        Req &q = p->reqs[*next];
+        const long long qn = (long long)q.r.Nr * q.r.Nz;
         if (p->used + q.bytes > p->budget || members >= p->max_members) break;
-        p->queue.pop_front();
+        if (p->node_window > 0 && p->nodes > 0 && p->nodes + qn > p->node_window) break;
+        p->queue.erase(next);
         const int rc = make_lattice(q, p->device);
         if (rc != AXLB_OK) {
             q.rc = rc;
@@ -182,6 +212,7 @@ int axlb_pool_tick(axlb_pool *p, int *running, int *queued) {
         }
         q.state = AXLB_REQ_RUNNING;
         p->used += q.bytes;
+        p->nodes += qn;
         p->dirty[q.r.storage] = true;
         ++members;
     }
@@ -238,6 +269,7 @@ int axlb_pool_tick(axlb_pool *p, int *running, int *queued) {
             axlb_destroy(q.lat);
             q.lat = nullptr;
             p->used -= q.bytes;
+            p->nodes -= (long long)q.r.Nr * q.r.Nz;
         }
     }
     int run = 0;

@@ -79,3 +79,28 @@ def test_step_each_matches_single_lattices(gpu):
         lat.step(37)
     for x, y in zip(a, ref):
         assert x.save() == y.save()
+
+
+def test_batched_workload_members_match_oracle(gpu, orc):
+    """The 256-instance batched workload stepped 1000 times in one fused
+    launch per step (100-step graph bundles): 8 sampled members against the
+    FP64 oracle (the 8 smallest, so that the oracle finishes in seconds), to
+    the FP32 parity bars."""
+    from test_gpu_parity import TOL, TOL_DRHO, assert_parity, field_errors
+    say("batched workload vs oracle")
+    from paper_1806_10241_amd import axlb
+    cases = I.batched_annuli(256, seed=4)
+    lats = [axlb.Lattice(c) for c in cases]
+    b = axlb.Batch(lats)
+    b.step(1000)
+    b.sync()
+    sample = sorted(range(len(cases)), key=lambda k: cases[k]["Nr"] * cases[k]["Nz"])[:8]
+    for k in sample:
+        c = cases[k]
+        ref = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
+        ref.step(1000)
+        got, want = lats[k].fields(), ref.fields()
+        say("  member %d (%d x %d): %s" % (k, c["Nr"], c["Nz"], {
+            f: "%.2e" % e for f, (e, _) in field_errors(got, want).items()}))
+        assert_parity(got, want, TOL["f32"], "member %d" % k, TOL_DRHO["f32"])
+    b.close()

@@ -70,3 +70,34 @@ def test_pool_rejects_requests_above_the_budget(gpu):
     with pytest.raises(axlb.AxlbError) as e:
         pool.submit(I.annulus_convection(Nr=256, Nz=256), "f32")
     assert e.value.code == axlb.ENOMEM
+
+
+def test_pool_smallest_first_with_node_window(gpu):
+    """SMALLEST_FIRST admits the least Nr*Nz*max_steps first, the node
+    window keeps the rest queued, and a request larger than the window runs
+    once it is alone; FIFO keeps arrival order."""
+    say("pool policy")
+    from paper_1806_10241_amd import axlb
+    big = I.annulus_convection(Nr=96, Nz=96, Ra=1e4, seed=71)
+    mid = I.annulus_convection(Nr=64, Nz=64, Ra=1e4, seed=72)
+    small = I.annulus_convection(Nr=32, Nz=48, Ra=1e4, seed=73)
+    for order, first in (("smallest", "small"), ("fifo", "big")):
+        pool = axlb.Pool(budget_bytes=1 << 30, order=order, node_window=64 * 64 + 32 * 48)
+        ids = {name: pool.submit(c, "f32", tol=0.0, max_steps=200)
+               for name, c in (("big", big), ("mid", mid), ("small", small))}
+        pool.tick()
+        running = {n for n, rid in ids.items() if pool.status(rid)[0] == axlb.REQ_RUNNING}
+        if order == "smallest":
+            assert running == {"small", "mid"}
+        else:
+            assert running == {"big"}          # the head blocks, and exceeds the window alone
+        for _ in range(40):
+            run, queued = pool.tick()
+            if run == 0 and queued == 0:
+                break
+        for name, rid in ids.items():
+            assert pool.status(rid)[0] == axlb.REQ_DONE and pool.status(rid)[1] == 200, name
+            pool.result(rid)
+        with pytest.raises(axlb.AxlbError):
+            pool.set_policy("fifo", -1)
+        pool.close()
