@@ -96,6 +96,21 @@ template <> struct Conv<float> {
     __device__ static __forceinline__ float ld(const float *p) { return *p; }
     __device__ static __forceinline__ void st(float *p, float v, unsigned) { *p = v; }
 };
+
+// 16-bit stores round stochastically with the gfx950 conversions
+// v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32: the result rounds away from zero
+// with probability equal to the discarded fraction, the threshold coming
+// from the top bits of the random operand.  The operand is a multiplicative
+// hash of the value's bits and the slot key, whose top bits are the well
+// mixed ones: rounding is deterministic (a checkpoint replays bit for bit)
+// and fresh whenever the value changes.  NaN stays NaN; values beyond the
+// format's range become infinite.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+typedef short short2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned sr_bits(float x, unsigned key) {
+    return (__float_as_uint(x) ^ key) * 0x9E3779B1U;
+}
+
 // binary16 holds the shifted populations scaled by 2^8 (exact), which keeps
 // values down to ~2e-7 out of the subnormal range; 2^8 * 64 still sits far
 // below the binary16 maximum for any population a stable run produces.
@@ -106,15 +121,8 @@ template <> struct Conv<__half> {
     }
     __device__ static __forceinline__ void st(__half *p, float v, unsigned key) {
         const float x = v * F16_SCALE;
-        if (!(fabsf(x) <= 65504.f)) {  // overflow and NaN keep their meaning
-            *p = __float2half_rn(x);
-            return;
-        }
-        const unsigned u = __float_as_uint(x);
-        // 13 = 23 - 10 mantissa bits dropped for a normal binary16; the top
-        // bits of a multiplicative hash of value and key
-        const unsigned r = ((u ^ key) * 0x9E3779B1U) >> 19;
-        *p = __float2half_rz(__uint_as_float(u + r));
+        const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(half2_t{0, 0}, x, sr_bits(x, key), false);
+        *p = __builtin_bit_cast(__half, h[0]);
     }
 };
 template <> struct Conv<__hip_bfloat16> {
@@ -122,14 +130,8 @@ template <> struct Conv<__hip_bfloat16> {
         return __bfloat162float(*p);
     }
     __device__ static __forceinline__ void st(__hip_bfloat16 *p, float v, unsigned key) {
-        const unsigned u = __float_as_uint(v);
-        if ((u & 0x7f800000U) == 0x7f800000U) {  // Inf / NaN
-            *p = __float2bfloat16(v);
-            return;
-        }
-        const unsigned r = ((u ^ key) * 0x9E3779B1U) >> 16;
-        const unsigned short h = (unsigned short)((u + r) >> 16);
-        *p = __builtin_bit_cast(__hip_bfloat16, h);
+        const short2_t b = __builtin_amdgcn_cvt_sr_bf16_f32(short2_t{0, 0}, v, sr_bits(v, key), false);
+        *p = __builtin_bit_cast(__hip_bfloat16, b[0]);
     }
 };
 
