@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--layout", default="aa", choices=["aa", "ab"])
+    ap.add_argument("--deriv", default="lagged", choices=["lagged", "current"],
+                    help="time level of the source-term derivatives (current needs --layout ab)")
     ap.add_argument("--Nr", type=int, default=1024)
     ap.add_argument("--Nz", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=10)
@@ -242,7 +244,8 @@ def main():
     case = I.rotating_lid_cylinder(Nr=args.Nr, Nz=args.Nz, Re=1000.0, Ri=0.5)
     nodes = case["Nr"] * case["Nz"]
     stream = torch.cuda.Stream()
-    lat = axlb.Lattice(case, storage=args.storage, layout=args.layout, stream=stream)
+    lat = axlb.Lattice(case, storage=args.storage, layout=args.layout, stream=stream,
+                       deriv=args.deriv)
     print("bench: %dx%d %s %s, warmup %d" % (args.Nr, args.Nz, args.storage, args.layout,
                                              args.warmup), file=sys.stderr, flush=True)
     if args.tile >= 0:
@@ -293,12 +296,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "rotating-lid cylinder with buoyancy, Re=1000, Ri=0.5, Pr=1",
                    "Nr": args.Nr, "Nz": args.Nz, "storage": args.storage,
-                   "layout": args.layout,
+                   "layout": args.layout, "derivatives": args.deriv,
                    "graph_bundle": 0 if args.single_launches else 100,
                    "tile": "%dx%d" % tile_rz, "autotune_us_per_step": tune},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": measured_traffic(args.storage, args.Nr, args.Nz)},
+                     "traffic": (measured_traffic(args.storage, args.Nr, args.Nz)
+                                 if args.layout == "aa" and args.deriv == "lagged" else None)},
         "finite": bool(r == r),
     }
     lat.close()

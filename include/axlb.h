@@ -53,6 +53,18 @@ extern "C" {
 #define AXLB_LAYOUT_AA 0 /* one population buffer, in place, alternating phases */
 #define AXLB_LAYOUT_AB 1 /* two population buffers, pull streaming              */
 
+/* ---- time level of the central differences in the geometric sources ----
+ * (eq. 4b, 4c, 7, 9; Section 3.2 only says "central difference").
+ * LAGGED: the previous step's pre-collision fields u_z, u_r, u_theta, T,
+ *   kept in a side buffer (either layout; the only form the single-buffer
+ *   layout allows, since in-place streaming overwrites a neighbour's
+ *   current populations).
+ * CURRENT: this step's output fields (after streaming, before the source
+ *   half step) of the neighbours; needs AXLB_LAYOUT_AB.
+ * The two share every steady state. */
+#define AXLB_DERIV_LAGGED 0
+#define AXLB_DERIV_CURRENT 1
+
 /* ---- geometry ---- */
 #define AXLB_ANNULUS 0  /* fluid between r = R_i and r = R_i + Nr            */
 #define AXLB_CYLINDER 1 /* fluid between the axis r = 0 and r = Nr           */
@@ -103,6 +115,7 @@ typedef struct {
                             must outlive the lattice; NULL: the library
                             allocates (and frees) its own                   */
     size_t device_bytes; /* size of device_buf                              */
+    int deriv;           /* AXLB_DERIV_LAGGED (default) | AXLB_DERIV_CURRENT */
 } axlb_options;
 
 /* Bytes of device memory a lattice of this size holds (populations, lagged
@@ -122,8 +135,10 @@ int axlb_state_bytes(int Nr, int Nz, int storage, int layout, size_t *bytes);
  *          g beta = Ra nu alpha / Nr^3; the buoyancy force is
  *          g beta (T - T0) along +z (eq. 5, F^b_x).
  *  Omega   angular velocity of OMEGA_R faces set with value NaN.
- *  w       relaxation rates (NULL: defaults); opt: storage/layout/stream
- *          (NULL: FP32, AA, T_ref = 0.5, own stream, current device).
+ *  w       relaxation rates (NULL: defaults); opt: storage/layout/stream/
+ *          derivative time level (NULL: FP32, AA, T_ref = 0.5, own stream,
+ *          current device, lagged); AXLB_EINVAL for CURRENT with the AA
+ *          layout.
  * Defaults: every face a no-slip wall with u_theta = 0 and zero heat flux;
  * a cylinder's inner face is the axis.  *out receives the handle. */
 int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, double alpha,

@@ -27,6 +27,7 @@ NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC = 0, 1, 2, 3, 4, 5
 
 STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
 LAYOUT = {"aa": LAYOUT_AA, "ab": LAYOUT_AB}
+DERIV = {"lagged": 0, "current": 1}
 
 # Every symbol include/axlb.h declares.
 EXPORTS = [
@@ -65,7 +66,7 @@ class Relax(C.Structure):
 class Options(C.Structure):
     _fields_ = [("storage", C.c_int), ("layout", C.c_int), ("T_ref", C.c_double),
                 ("stream", C.c_void_p), ("device", C.c_int), ("device_buf", C.c_void_p),
-                ("device_bytes", C.c_size_t)]
+                ("device_bytes", C.c_size_t), ("deriv", C.c_int)]
 
 
 class Request(C.Structure):
@@ -175,12 +176,15 @@ class Lattice:
     ``paper_1806_10241_amd.inputs``.
 
     storage: "f32" | "f16" | "bf16"; layout: "aa" (one buffer) | "ab".
+    deriv: "lagged" (previous-step fields) | "current" (this step's output
+    fields; needs layout "ab").
     stream: a ``torch.cuda.Stream`` to run on (None: the library's own).
     torch_memory: lend the state as a torch CUDA tensor (else hipMalloc).
     """
 
     def __init__(self, case: dict, storage: str = "f32", layout: str = "aa", stream=None,
-                 device: int = 0, torch_memory: bool = True, init_fields: bool = True):
+                 device: int = 0, torch_memory: bool = True, init_fields: bool = True,
+                 deriv: str = "lagged"):
         lib = load()
         self._lib = lib
         self._h = _vp()
@@ -192,6 +196,7 @@ class Lattice:
         opt = Options()
         opt.storage = STORAGE[storage]
         opt.layout = LAYOUT[layout]
+        opt.deriv = DERIV[deriv]
         opt.T_ref = float(case.get("T_ref", 0.5))
         opt.device = int(device)
         self._stream = stream

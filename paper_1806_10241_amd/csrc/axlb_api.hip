@@ -125,7 +125,9 @@ static int launch_one(axlb_lattice *L, long t) {
     const int par = (int)(t & 1);
     LagT *Mprev = L->lag[par], *Mnext = L->lag[par ^ 1];
     hipError_t e;
-    if (L->layout == AXLB_LAYOUT_AA)
+    if (L->deriv == AXLB_DERIV_CURRENT)
+        e = launch_step_current(P, L->storage, L->tile, L->pop[par], L->pop[par ^ 1], L->stream);
+    else if (L->layout == AXLB_LAYOUT_AA)
         e = launch_step(P, L->storage, L->tile, par == 0 ? 1 : 2, L->pop[0], L->pop[0], Mprev,
                         Mnext, L->stream);
     else
@@ -175,7 +177,9 @@ static int compute_fields(axlb_lattice *L) {
     const long t = L->steps;
     const int par = (int)(t & 1);
     hipError_t e;
-    if (L->layout == AXLB_LAYOUT_AA)
+    if (L->deriv == AXLB_DERIV_CURRENT)
+        e = launch_fields_current(L->P, L->storage, L->pop[par], L->fld, L->stream);
+    else if (L->layout == AXLB_LAYOUT_AA)
         e = launch_fields(L->P, L->storage, par == 0 ? 1 : 2, L->pop[0], L->lag[par], L->fld,
                           L->stream);
     else
@@ -245,6 +249,10 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     if (opt) O = *opt;
     if (O.storage < 0 || O.storage > 2) return fail(nullptr, AXLB_EINVAL, "unknown storage");
     if (O.layout < 0 || O.layout > 1) return fail(nullptr, AXLB_EINVAL, "unknown layout");
+    if (O.deriv != AXLB_DERIV_LAGGED && O.deriv != AXLB_DERIV_CURRENT)
+        return fail(nullptr, AXLB_EINVAL, "unknown derivative time level");
+    if (O.deriv == AXLB_DERIV_CURRENT && O.layout != AXLB_LAYOUT_AB)
+        return fail(nullptr, AXLB_EINVAL, "current-step derivatives need the two-buffer layout");
     if (!std::isfinite(O.T_ref)) return fail(nullptr, AXLB_EINVAL, "T_ref must be finite");
 
     axlb_lattice *L = new (std::nothrow) axlb_lattice();
@@ -262,6 +270,7 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     L->relax = R;
     L->storage = O.storage;
     L->layout = O.layout;
+    L->deriv = O.deriv;
     L->T_ref = O.T_ref;
     for (int f = 0; f < 4; ++f) {
         L->kind[f][0] = AXLB_NOSLIP;

@@ -29,7 +29,7 @@ struct axlb_lattice {
     double r_inner = 0, nu = 0, alpha = 0, Ra = 0, Omega = 0, gbeta = 0, g_axial = 0, T0 = 0.5;
     double T_ref = 0.5;
     axlb_relax relax{};
-    int storage = 0, layout = 0;
+    int storage = 0, layout = 0, deriv = 0;
     int kind[4][3]{};
     double val[4][3]{};
     int device = 0;

@@ -222,10 +222,6 @@ static dim3 grid_for(const KParams &P, int bx, int by) {
 
 static dim3 step_grid(const KParams &P) { return grid_for(P, TX, TY); }
 
-// Tile shapes (r x z) of the step kernel that the autotuner chooses from.
-#define AXLB_TILES(X) X(0, 64, 4) X(1, 64, 2) X(2, 64, 8) X(3, 128, 2) X(4, 256, 1) \
-    X(5, 64, 1) X(6, 128, 4) X(7, 32, 8)
-
 template <class S, int BX, int BY>
 static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT *Mprev,
                              LagT *Mnext, hipStream_t st) {

@@ -11,6 +11,8 @@ namespace axlb {
 enum { STORE_F32 = 0, STORE_F16 = 1, STORE_BF16 = 2 };
 
 // Tile shapes of the step kernel: tile_shape(t) gives r x z nodes per workgroup.
+#define AXLB_TILES(X) X(0, 64, 4) X(1, 64, 2) X(2, 64, 8) X(3, 128, 2) X(4, 256, 1) \
+    X(5, 64, 1) X(6, 128, 4) X(7, 32, 8)
 constexpr int NTILES = 8;
 int tile_count();
 void tile_shape(int tile, int *bx, int *by);
@@ -20,6 +22,12 @@ hipError_t launch_step(const KParams &P, int storage, int tile, int mode, void *
                        const LagT *Mprev, LagT *Mnext, hipStream_t st);
 hipError_t launch_fields(const KParams &P, int storage, int mode, const void *src,
                          const LagT *Mprev, double *out, hipStream_t st);
+// Current-step derivatives (two buffers, pull): one step src -> dst, or the
+// reported fields of the state in src.
+hipError_t launch_step_current(const KParams &P, int storage, int tile, const void *src,
+                               void *dst, hipStream_t st);
+hipError_t launch_fields_current(const KParams &P, int storage, const void *src, double *out,
+                                 hipStream_t st);
 hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
                        LagT *M, hipStream_t st);
 hipError_t launch_residual(const double *fld, const double *snap, long long N, double *part,

@@ -163,22 +163,23 @@ __device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float
 }
 
 // ----------------------------------------------------------------------------
-// Lagged derivative field v (0 u_x, 1 u_y, 2 u_theta, 3 T - T_ref) at the
-// neighbour (i + di, j + dj); outside the fluid a ghost value mirrored
-// through the half-way wall: -q for u_x, u_y at a no-slip wall, 2 q_w - q
-// for an imposed u_theta or T, q for zero flux; q (u_x, T) or -q (u_y,
-// u_theta) at the axis; the wrapped node on a periodic face.
-__device__ __forceinline__ float lag_edge(const KParams &P, const LagT *M, int v, int i, int j,
+// Derivative field v (0 u_x, 1 u_y, 2 u_theta, 3 T - T_ref) at the
+// neighbour (i + di, j + dj) of fluid node (i, j).  get(v, di, dj) returns
+// the field at a fluid neighbour, or at the periodic image of a neighbour
+// beyond a periodic face; beyond a wall or the axis the value is a ghost
+// mirrored through the half-way wall: -q for u_x, u_y at a no-slip wall,
+// 2 q_w - q for an imposed u_theta or T, q for zero flux; q (u_x, T) or -q
+// (u_y, u_theta) at the axis, with q = get(v, 0, 0) the node's own value.
+template <class Get>
+__device__ __forceinline__ float field_at(const KParams &P, const Get &get, int v, int i, int j,
                                           int di, int dj) {
     const int ni = i + di, nj = j + dj;
-    const float q1 = lag_ld(M, v, P.plane, (long long)i * P.pitch + j);
+    if ((unsigned)ni < (unsigned)P.Nz && (unsigned)nj < (unsigned)P.Nr) return get(v, di, dj);
     const int face = nj < 0 ? R_IN : (nj >= P.Nr ? R_OUT : (ni < 0 ? Z_LO : Z_HI));
     const int fld = v <= 1 ? FLOW : (v == 2 ? SWIRL : THERMAL);
     const int k = kind_of(P, face, fld);
-    if (k == PERIODIC) {
-        const int wi = ni < 0 ? ni + P.Nz : ni - P.Nz;
-        return lag_ld(M, v, P.plane, (long long)wi * P.pitch + nj);
-    }
+    if (k == PERIODIC) return get(v, di, dj);
+    const float q1 = get(v, 0, 0);
     if (k == MIRROR) return (v == 0 || v == 3) ? q1 : -q1;
     if (k == ADIABATIC) return q1;
     if (v <= 1) return -q1;
@@ -187,13 +188,31 @@ __device__ __forceinline__ float lag_edge(const KParams &P, const LagT *M, int v
     return 2.f * s - q1;
 }
 
-__device__ __forceinline__ float lag(const KParams &P, const LagT *M, int v, int i, int j, int di,
-                                     int dj) {
-    const int ni = i + di, nj = j + dj;
-    if ((unsigned)ni < (unsigned)P.Nz && (unsigned)nj < (unsigned)P.Nr)
-        return lag_ld(M, v, P.plane, (long long)ni * P.pitch + nj);
-    return lag_edge(P, M, v, i, j, di, dj);
+// Central differences d = {d_x u_y, d_y u_x, d_y u_y, d_y u_theta, d_y T}
+// at fluid node (i, j) from a field source as in field_at.
+template <class Get>
+__device__ __forceinline__ void differences(const KParams &P, const Get &get, int i, int j,
+                                            float d[5]) {
+    d[0] = 0.5f * (field_at(P, get, 1, i, j, +1, 0) - field_at(P, get, 1, i, j, -1, 0));
+    d[1] = 0.5f * (field_at(P, get, 0, i, j, 0, +1) - field_at(P, get, 0, i, j, 0, -1));
+    d[2] = 0.5f * (field_at(P, get, 1, i, j, 0, +1) - field_at(P, get, 1, i, j, 0, -1));
+    d[3] = 0.5f * (field_at(P, get, 2, i, j, 0, +1) - field_at(P, get, 2, i, j, 0, -1));
+    d[4] = 0.5f * (field_at(P, get, 3, i, j, 0, +1) - field_at(P, get, 3, i, j, 0, -1));
 }
+
+// The lagged fields of the previous step as a field source (periodic
+// images wrap along z).
+struct LagSource {
+    const KParams &P;
+    const LagT *M;
+    int i, j;
+    __device__ __forceinline__ float operator()(int v, int di, int dj) const {
+        int ni = i + di;
+        if (ni < 0) ni += P.Nz;
+        else if (ni >= P.Nz) ni -= P.Nz;
+        return lag_ld(M, v, P.plane, (long long)ni * P.pitch + (j + dj));
+    }
+};
 
 // ----------------------------------------------------------------------------
 // The pre-collision half step (eq. 21, 38, 48) with the geometric sources of
@@ -356,11 +375,7 @@ __device__ __forceinline__ void derivatives(const KParams &P, const LagT *M, int
         d[4] = 0.5f * (Mp[n + 1] - Mp[n - 1]);
         return;
     }
-    d[0] = 0.5f * (lag(P, M, 1, i, j, +1, 0) - lag(P, M, 1, i, j, -1, 0));  // d_x u_y
-    d[1] = 0.5f * (lag(P, M, 0, i, j, 0, +1) - lag(P, M, 0, i, j, 0, -1));  // d_y u_x
-    d[2] = 0.5f * (lag(P, M, 1, i, j, 0, +1) - lag(P, M, 1, i, j, 0, -1));  // d_y u_y
-    d[3] = 0.5f * (lag(P, M, 2, i, j, 0, +1) - lag(P, M, 2, i, j, 0, -1));  // d_y u_theta
-    d[4] = 0.5f * (lag(P, M, 3, i, j, 0, +1) - lag(P, M, 3, i, j, 0, -1));  // d_y T
+    differences(P, LagSource{P, M, i, j}, i, j, d);
 }
 
 // ----------------------------------------------------------------------------

@@ -49,3 +49,20 @@ def test_state_bytes_and_argument_checks():
     rc = lib.axlb_lattice_create(32, 8, C.byref(geo), 0.1, 0.1, 0.7, 0.0, 0.0, None, None,
                                  C.byref(out))
     assert rc == axlb.EINVAL  # Pr != nu/alpha
+
+
+def test_current_derivatives_rejected_with_one_buffer():
+    """Option validation happens before any device call: current-step
+    derivatives with the single-buffer layout, and an unknown time level,
+    are refused with AXLB_EINVAL."""
+    import ctypes as C
+    from paper_1806_10241_amd import axlb
+    lib = axlb.load()
+    geo = axlb.Geometry(axlb.ANNULUS, 10.0)
+    for layout, deriv in ((axlb.LAYOUT_AA, 1), (axlb.LAYOUT_AB, 2)):
+        opt = axlb.Options()
+        opt.layout, opt.deriv, opt.T_ref, opt.device = layout, deriv, 0.5, 0
+        h = C.c_void_p()
+        rc = lib.axlb_lattice_create(30, 8, C.byref(geo), 0.1, 0.1, 0.0, 0.0, float("nan"), None,
+                                     C.byref(opt), C.byref(h))
+        assert rc == axlb.EINVAL and not h.value
