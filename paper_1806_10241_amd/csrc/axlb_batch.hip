@@ -1,6 +1,6 @@
 // Batched stepping of many independent lattices of uneven size: every step
 // of every member runs in one fused launch over a work-list of (member,
-// tile) pairs, 100-step bundles are captured as HIP graphs, and the tile
+// tile) pairs (chunks of a member's edge nodes, then its tiles), 100-step bundles are captured as HIP graphs, and the tile
 // shape and the launch schedule come from an autotuner.  The node update is
 // the one of the single-lattice kernels (axlb_node.h), so a member's result
 // does not depend on whether it ran alone or in a batch.
@@ -26,7 +26,7 @@ struct InstDesc {
     int parity0;     // member step count at batch creation, mod 2
     int tile_begin;  // first work-list entry of this member
     int gx;          // tiles along r
-    int pad;
+    int nedge;       // edge chunks, the member's first work-list entries
 };
 
 // Work-list entries are dealt to the 8 XCDs in 8 contiguous chunks, so that
@@ -44,14 +44,27 @@ __global__ void __launch_bounds__(BX *BY)
     for (int t = lo + k; t < hi; t += nbx) {
         const InstDesc *d = D + tile_inst[t];
         const int local = t - d->tile_begin;
-        const int j = (local % d->gx) * BX + (int)threadIdx.x % BX;
-        const int i = (local / d->gx) * BY + (int)threadIdx.x / BX;
-        if (i >= d->P.Nz || j >= d->P.Nr) continue;
+        const bool odd = (d->parity0 ^ phase) == 0;
         S *A = (S *)d->pop;
-        if ((d->parity0 ^ phase) == 0)
-            update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j);
-        else
-            update_node<S, MODE_AA_EVEN>(d->P, A, A, d->lag[1], d->lag[0], i, j);
+        if (local < d->nedge) {  // edge nodes: their own entries in the odd phase only
+            const int e = local * (BX * BY) + (int)threadIdx.x;
+            if (!odd || e >= edge_count(d->P.Nr, d->P.Nz)) continue;
+            int i, j;
+            edge_node(d->P, e, i, j);
+            update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j, false);
+            continue;
+        }
+        const int u = local - d->nedge;
+        const int j = (u % d->gx) * BX + (int)threadIdx.x % BX;
+        const int i = (u / d->gx) * BY + (int)threadIdx.x / BX;
+        if (odd) {
+            if (!interior_node(d->P, i, j)) continue;
+            update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j, true);
+        } else {
+            if (i >= d->P.Nz || j >= d->P.Nr) continue;
+            update_node<S, MODE_AA_EVEN>(d->P, A, A, d->lag[1], d->lag[0], i, j,
+                                         interior_node(d->P, i, j));
+        }
     }
 }
 
@@ -141,8 +154,9 @@ static int build_worklist(axlb_batch *b) {
         d.parity0 = (int)((L->steps - b->steps) & 1);
         d.gx = (L->Nr + bx - 1) / bx;
         const int gy = (L->Nz + by - 1) / by;
+        d.nedge = (edge_count(L->Nr, L->Nz) + bx * by - 1) / (bx * by);
         d.tile_begin = (int)tiles.size();
-        tiles.insert(tiles.end(), (size_t)d.gx * gy, (int)m);
+        tiles.insert(tiles.end(), (size_t)d.nedge + (size_t)d.gx * gy, (int)m);
     }
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);

@@ -23,15 +23,41 @@
 
 namespace axlb {
 
-// One time step for every node of one lattice.
+// One time step for every node of one lattice.  Where boundary rules apply
+// to the streaming (AA odd phase, AB), the first workgroups take BX * BY
+// consecutive edge nodes each (their count rounded up to a multiple of 8,
+// so that the hardware deals them to all eight XCDs and the tiles after
+// them keep their XCD alignment), and the tile workgroups skip the edge
+// nodes; the AA even phase streams within each node's own slots, so its
+// tiles take every node.  Tile workgroups are XCD-remapped as in tile_of.
 template <class S, int MODE, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const S *src, S *dst,
                                                    const LagT *__restrict__ Mprev,
                                                    LagT *__restrict__ Mnext) {
-    int i, j;
-    tile_of<BX, BY>(P, i, j);
-    if (i >= P.Nz || j >= P.Nr) return;
-    update_node<S, MODE>(P, src, dst, Mprev, Mnext, i, j);
+    constexpr bool SPLIT = MODE != MODE_AA_EVEN;
+    const int gx = (P.Nr + BX - 1) / BX;
+    const int ne = SPLIT ? edge_blocks(P.Nr, P.Nz, BX * BY) : 0;
+    const int b = (int)blockIdx.x;
+    if (SPLIT && b < ne) {
+        const int e = b * (BX * BY) + (int)threadIdx.x;
+        if (e >= edge_count(P.Nr, P.Nz)) return;
+        int i, j;
+        edge_node(P, e, i, j);
+        update_node<S, MODE>(P, src, dst, Mprev, Mnext, i, j, false);
+        return;
+    }
+    const int nb = (int)gridDim.x - ne, bt = b - ne;
+    const int xcd = bt & 7, k = bt >> 3, q = nb >> 3, r = nb & 7;
+    const int u = xcd * q + (xcd < r ? xcd : r) + k;
+    const int j = (u % gx) * BX + (int)threadIdx.x % BX;
+    const int i = (u / gx) * BY + (int)threadIdx.x / BX;
+    if (SPLIT) {
+        if (!interior_node(P, i, j)) return;  // edge nodes and the ragged tail
+        update_node<S, MODE>(P, src, dst, Mprev, Mnext, i, j, true);
+    } else {
+        if (i >= P.Nz || j >= P.Nr) return;
+        update_node<S, MODE>(P, src, dst, Mprev, Mnext, i, j, interior_node(P, i, j));
+    }
 }
 
 // The fields the next step's collision sees, without changing the state:
@@ -225,7 +251,8 @@ static dim3 step_grid(const KParams &P) { return grid_for(P, TX, TY); }
 template <class S, int BX, int BY>
 static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT *Mprev,
                              LagT *Mnext, hipStream_t st) {
-    const dim3 grid = grid_for(P, BX, BY), block(BX * BY);
+    const int edges = mode == MODE_AA_EVEN ? 0 : edge_blocks(P.Nr, P.Nz, BX * BY);
+    const dim3 grid(grid_for(P, BX, BY).x + edges), block(BX * BY);
     switch (mode) {
     case MODE_AB: k_step<S, MODE_AB, BX, BY><<<grid, block, 0, st>>>(P, a, b, Mprev, Mnext); break;
     case MODE_AA_ODD: k_step<S, MODE_AA_ODD, BX, BY><<<grid, block, 0, st>>>(P, a, a, Mprev, Mnext); break;

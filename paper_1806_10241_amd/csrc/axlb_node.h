@@ -550,14 +550,40 @@ __device__ __forceinline__ bool interior_node(const KParams &P, int i, int j) {
     return (unsigned)(i - 1) < (unsigned)(P.Nz - 2) && (unsigned)(j - 1) < (unsigned)(P.Nr - 2);
 }
 
+// The nodes on the edge of a lattice, where boundary rules may apply:
+// columns j = 0 and j = Nr - 1 (every row), then rows i = 0 and i = Nz - 1
+// without their end nodes (one row when Nz = 1).  Every other node is
+// interior_node.  Edge nodes run in workgroups of their own, so that the
+// waves of interior tiles never diverge into the boundary code.
+__host__ __device__ __forceinline__ int edge_count(int Nr, int Nz) {
+    return 2 * Nz + (Nr - 2) * (Nz >= 2 ? 2 : 1);
+}
+// Workgroups of `threads` that the edge nodes of one lattice take in a
+// single-lattice launch: a multiple of 8 (one per XCD in turn).
+__host__ __device__ __forceinline__ int edge_blocks(int Nr, int Nz, int threads) {
+    return ((edge_count(Nr, Nz) + threads - 1) / threads + 7) / 8 * 8;
+}
+__device__ __forceinline__ void edge_node(const KParams &P, int e, int &i, int &j) {
+    if (e < 2 * P.Nz) {
+        j = e < P.Nz ? 0 : P.Nr - 1;
+        i = e < P.Nz ? e : e - P.Nz;
+        return;
+    }
+    e -= 2 * P.Nz;
+    const int w = P.Nr - 2;
+    i = e < w ? 0 : P.Nz - 1;
+    j = 1 + (e < w ? e : e - w);
+}
+
 // One time step of node (i, j): stream (gather), output moments, half
 // source step, cascaded collisions with the source moments, store; the
 // node's half-step fields go to the lagged buffer of the next step.
+// `interior` must equal interior_node(P, i, j); callers pass a constant.
 template <class S, int MODE>
 __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *dst,
                                             const LagT *__restrict__ Mprev,
-                                            LagT *__restrict__ Mnext, int i, int j) {
-    const bool interior = interior_node(P, i, j);
+                                            LagT *__restrict__ Mnext, int i, int j,
+                                            bool interior) {
     float f[9], g[5], h[5];
     gather<S, MODE>(P, src, i, j, interior, f, g, h);
     const Moments m = moments(f, g, h);
