@@ -104,3 +104,28 @@ def test_steady_nusselt_matches_oracle(gpu, orc):
     say("  gpu", a, "oracle", b)
     for x, y in zip(a, b):
         assert abs(x - y) <= 5e-3 * abs(y)
+
+
+@pytest.mark.parametrize("beta", [0.103, 0.203, 0.303, 0.503])
+def test_couette_radius_ratio_sweep_at_paper_resolution(gpu, beta):
+    """Section 3.1, Figure 1: u_theta = A r + B / r between cylinders with
+    R_o at 200 nodes, kappa = 0.1, Re = 5, tau = 0.6, three periodic rows;
+    started from the linear profile between the wall speeds, run to
+    residual 1e-10 (the slowest mode then sits ~1e-5 from the end state).
+    Second order from 24 rows (the oracle's pin) gives about 1.5e-4 here at
+    the smallest ratio."""
+    say("couette sweep, beta", beta)
+    from paper_1806_10241_amd import axlb
+    from test_oracle_lattice import couette_case, couette_profile
+    Nr = int(round(200 * (1 - beta)))
+    c, Ri, Ro, u_o = couette_case(beta, Nr, Nz=3)
+    r = Ri + np.arange(Nr) + 0.5
+    lin = u_o + (0.1 * u_o / beta - u_o) * (r - Ri) / (Ro - Ri)
+    lat = axlb.Lattice(c, init_fields=False)
+    lat.set_fields(uth=np.tile(lin, (3, 1)), T=np.full((3, Nr), 0.5))
+    res = run_to_steady(lat, tol=1e-10, chunk=20000, max_steps=6_000_000)
+    got = lat.fields()["uth"][1]
+    exact = couette_profile(beta, 0.1, Ri, Ro, u_o, r)
+    err = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+    say("  Nr %d steps %d residual %.1e rel L2 %.2e" % (Nr, lat.steps, res, err))
+    assert res < 1e-10 and err < 5e-4
