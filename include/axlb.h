@@ -207,9 +207,13 @@ int axlb_autotune(axlb_lattice *lat, int steps_per_trial, double *ms_per_step, i
 void axlb_destroy(axlb_lattice *lat);
 
 /* ---- batches of independent lattices (uneven sizes) ----
- * A batch advances all its member lattices together: every step of every
- * member is one fused launch over a work-list of (member, tile) entries, and
- * 100-step bundles are captured as HIP graphs.  Members must share device
+ * A batch advances all its member lattices together: a step of many members
+ * is one fused launch over a work-list of (member, tile) entries, and
+ * 100-step bundles are captured as HIP graphs.  Within a bundle, runs of
+ * consecutive members whose states total at most 160 MB (below the 256 MB
+ * Infinity Cache) take all 100 steps before the next run starts; after
+ * axlb_batch_step every member has advanced by the same count either way.
+ * Members must share device
  * and storage, use the AA layout and belong to no other batch; their
  * boundary rules are locked.  While batched, a member runs on the batch's
  * stream: axlb_get_moments, axlb_nusselt, axlb_residual and axlb_save work

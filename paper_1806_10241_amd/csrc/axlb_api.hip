@@ -118,8 +118,9 @@ static int check_bcs(axlb_lattice *L) {
     return AXLB_OK;
 }
 
-// HIP graph of BUNDLE consecutive steps starting at an even (k = 0) or odd
-// (k = 1) step count; BUNDLE is even, so every buffer role recurs.
+// The kernel launch of step t (counted from the lattice's creation): the
+// parity of t selects the AA phase, or which buffer is read, and which
+// lagged-field block is read and which written.
 static int launch_one(axlb_lattice *L, long t) {
     const KParams &P = L->P;
     const int par = (int)(t & 1);
@@ -137,6 +138,8 @@ static int launch_one(axlb_lattice *L, long t) {
     return AXLB_OK;
 }
 
+// HIP graph of BUNDLE consecutive steps starting at an even (k = 0) or odd
+// (k = 1) step count; BUNDLE is even, so every buffer role recurs.
 static int ensure_graph(axlb_lattice *L, int k) {
     if (L->graph_exec[k]) return AXLB_OK;
     HIP_TRY(L, hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));

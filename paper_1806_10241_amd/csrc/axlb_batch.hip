@@ -1,9 +1,14 @@
-// Batched stepping of many independent lattices of uneven size: every step
-// of every member runs in one fused launch over a work-list of (member,
-// tile) pairs (chunks of a member's edge nodes, then its tiles), 100-step bundles are captured as HIP graphs, and the tile
-// shape and the launch schedule come from an autotuner.  The node update is
-// the one of the single-lattice kernels (axlb_node.h), so a member's result
-// does not depend on whether it ran alone or in a batch.
+// Batched stepping of many independent lattices of uneven size.  A step of
+// many members runs as one fused launch over a work-list of (member, tile)
+// pairs (chunks of a member's edge nodes, then its tiles).  100-step bundles
+// are captured as HIP graphs; within a bundle, consecutive members whose
+// state fits the Infinity Cache together form a group that takes all 100
+// steps before the next group starts, so the state of the running group
+// stays in that cache (the members are independent, so their steps need no
+// common order).  The tile shape and the launch schedule come from an
+// autotuner.  The node update is the one of the single-lattice kernels
+// (axlb_node.h), so a member's result does not depend on whether it ran
+// alone or in a batch.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -17,6 +22,10 @@
 #include "axlb_node.h"
 
 namespace axlb {
+
+// State bytes of the members that one group holds: below MI355X's 256 MB
+// Infinity Cache, with room for the other traffic of a step.
+constexpr size_t GROUP_BYTES = 160u << 20;
 
 // Per-member descriptor in device memory.
 struct InstDesc {
@@ -35,12 +44,13 @@ struct InstDesc {
 // as entries every block takes one tile; with fewer, blocks persist and loop.
 template <class S, int BX, int BY>
 __global__ void __launch_bounds__(BX *BY)
-    k_step_batch(const InstDesc *__restrict__ D, const int *__restrict__ tile_inst, int ntiles,
-                 int phase) {
+    k_step_batch(const InstDesc *__restrict__ D, const int *__restrict__ tile_inst, int t0,
+                 int ntiles, int phase) {
     const int G = gridDim.x, b = blockIdx.x;
     const int xcd = b & 7, k = b >> 3;
     const int nbx = (G >> 3) + (xcd < (G & 7) ? 1 : 0);
-    const int lo = (int)((long long)ntiles * xcd / 8), hi = (int)((long long)ntiles * (xcd + 1) / 8);
+    const int lo = t0 + (int)((long long)ntiles * xcd / 8);
+    const int hi = t0 + (int)((long long)ntiles * (xcd + 1) / 8);
     for (int t = lo + k; t < hi; t += nbx) {
         const InstDesc *d = D + tile_inst[t];
         const int local = t - d->tile_begin;
@@ -73,11 +83,11 @@ __global__ void __launch_bounds__(BX *BY)
 
 template <class S>
 static hipError_t launch_batch_t(int tile, int blocks, const InstDesc *D, const int *tiles,
-                                 int ntiles, int phase, hipStream_t st) {
+                                 int t0, int ntiles, int phase, hipStream_t st) {
     switch (tile) {
 #define AXLB_CASE(id, bx, by)                                                               \
     case id:                                                                                \
-        k_step_batch<S, bx, by><<<blocks, bx * by, 0, st>>>(D, tiles, ntiles, phase); \
+        k_step_batch<S, bx, by><<<blocks, bx * by, 0, st>>>(D, tiles, t0, ntiles, phase); \
         break;
         AXLB_BATCH_TILES(AXLB_CASE)
 #undef AXLB_CASE
@@ -87,11 +97,12 @@ static hipError_t launch_batch_t(int tile, int blocks, const InstDesc *D, const 
 }
 
 static hipError_t launch_batch(int storage, int tile, int blocks, const InstDesc *D,
-                               const int *tiles, int ntiles, int phase, hipStream_t st) {
-    if (storage == STORE_F16) return launch_batch_t<__half>(tile, blocks, D, tiles, ntiles, phase, st);
+                               const int *tiles, int t0, int ntiles, int phase, hipStream_t st) {
+    if (storage == STORE_F16)
+        return launch_batch_t<__half>(tile, blocks, D, tiles, t0, ntiles, phase, st);
     if (storage == STORE_BF16)
-        return launch_batch_t<__hip_bfloat16>(tile, blocks, D, tiles, ntiles, phase, st);
-    return launch_batch_t<float>(tile, blocks, D, tiles, ntiles, phase, st);
+        return launch_batch_t<__hip_bfloat16>(tile, blocks, D, tiles, t0, ntiles, phase, st);
+    return launch_batch_t<float>(tile, blocks, D, tiles, t0, ntiles, phase, st);
 }
 
 }  // namespace axlb
@@ -109,6 +120,10 @@ struct axlb_batch {
     InstDesc *d_desc = nullptr;
     int *d_tiles = nullptr;
     int ntiles = 0;
+    // work-list ranges of consecutive members whose state fits the
+    // Infinity Cache together: a bundle runs all its steps on one group
+    // before the next; group g is entries [group[g], group[g + 1])
+    std::vector<int> group;
     long steps = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     std::string err;
@@ -143,6 +158,8 @@ static int build_worklist(axlb_batch *b) {
     tile_shape(b->tile, &bx, &by);
     std::vector<InstDesc> desc(b->members.size());
     std::vector<int> tiles;
+    b->group.clear();
+    size_t group_bytes = 0;
     for (size_t m = 0; m < b->members.size(); ++m) {
         axlb_lattice *L = b->members[m];
         InstDesc &d = desc[m];
@@ -157,7 +174,14 @@ static int build_worklist(axlb_batch *b) {
         d.nedge = (edge_count(L->Nr, L->Nz) + bx * by - 1) / (bx * by);
         d.tile_begin = (int)tiles.size();
         tiles.insert(tiles.end(), (size_t)d.nedge + (size_t)d.gx * gy, (int)m);
+        const size_t bytes = L->lay.pop_bytes + 2 * L->lay.lag_bytes;
+        if (m == 0 || group_bytes + bytes > GROUP_BYTES) {
+            b->group.push_back(d.tile_begin);
+            group_bytes = 0;
+        }
+        group_bytes += bytes;
     }
+    b->group.push_back((int)tiles.size());
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     b->d_desc = nullptr;
@@ -174,14 +198,18 @@ static int build_worklist(axlb_batch *b) {
     return AXLB_OK;
 }
 
-static int batch_launch(axlb_batch *b, long s) {
-    int blocks = b->blocks > 0 ? b->blocks : b->ntiles;
+// One step (parity s & 1) of the work-list entries [t0, t1).
+static int batch_launch(axlb_batch *b, long s, int t0, int t1) {
+    const int n = t1 - t0;
+    int blocks = b->blocks > 0 ? b->blocks : n;
     if (blocks < 8) blocks = 8;  // every XCD chunk needs a block
-    hipError_t e = launch_batch(b->storage, b->tile, blocks, b->d_desc, b->d_tiles, b->ntiles,
+    hipError_t e = launch_batch(b->storage, b->tile, blocks, b->d_desc, b->d_tiles, t0, n,
                                 (int)(s & 1), b->stream);
     if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     return AXLB_OK;
 }
+
+static int batch_launch(axlb_batch *b, long s) { return batch_launch(b, s, 0, b->ntiles); }
 
 static void advance_members(axlb_batch *b, long n) {
     b->steps += n;
@@ -276,8 +304,12 @@ int axlb_batch_step(axlb_batch *b, long n) {
             const int k = (int)(b->steps & 1);
             if (!b->graph[k]) {
                 BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                // group by group: each group's state stays in the Infinity
+                // Cache for the whole bundle
                 int rc = AXLB_OK;
-                for (long s = 0; s < BUNDLE && rc == AXLB_OK; ++s) rc = batch_launch(b, k + s);
+                for (size_t g = 0; g + 1 < b->group.size() && rc == AXLB_OK; ++g)
+                    for (long s = 0; s < BUNDLE && rc == AXLB_OK; ++s)
+                        rc = batch_launch(b, k + s, b->group[g], b->group[g + 1]);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(b->stream, &g);
                 if (rc != AXLB_OK) {
