@@ -191,7 +191,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--layout", default="aa", choices=["aa", "ab"])
+    ap.add_argument("--layout", default="aa", choices=["aa", "ab", "ab2"])
     ap.add_argument("--deriv", default="lagged", choices=["lagged", "current"],
                     help="time level of the source-term derivatives (current needs --layout ab)")
     ap.add_argument("--Nr", type=int, default=1024)

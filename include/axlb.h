@@ -52,6 +52,13 @@ extern "C" {
 /* ---- streaming layouts ---- */
 #define AXLB_LAYOUT_AA 0 /* one population buffer, in place, alternating phases */
 #define AXLB_LAYOUT_AB 1 /* two population buffers, pull streaming              */
+#define AXLB_LAYOUT_AB2 2 /* two buffers, two time steps per launch (below)     */
+/* AXLB_LAYOUT_AB2 holds the same two buffers as AB.  One launch advances two
+ * time steps: a workgroup takes its tile and a one-node ring around it
+ * through the first step, keeping the populations and lagged fields in
+ * LDS, then takes its tile through the second step.  The results are
+ * bit-identical to AB; each pair of steps reads and writes the state once.
+ * An odd step count ends with one AB step. */
 
 /* ---- time level of the central differences in the geometric sources ----
  * (eq. 4b, 4c, 7, 9; Section 3.2 only says "central difference").
@@ -106,7 +113,7 @@ typedef struct {
 
 typedef struct {
     int storage;  /* AXLB_F32 | AXLB_F16 | AXLB_BF16                         */
-    int layout;   /* AXLB_LAYOUT_AA (default) | AXLB_LAYOUT_AB                */
+    int layout;   /* AXLB_LAYOUT_AA (default) | AXLB_LAYOUT_AB | AXLB_LAYOUT_AB2 */
     double T_ref; /* temperature about which h is stored (shifted storage)   */
     void *stream; /* hipStream_t to run on; NULL: the library makes its own  */
     int device;   /* HIP device ordinal; -1: the current device              */

@@ -19,14 +19,14 @@ LIB_PATH = os.path.join(_HERE, "libaxlb.so")
 
 OK, EINVAL, ENOMEM, EUNSTABLE, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 F32, F16, BF16 = 0, 1, 2
-LAYOUT_AA, LAYOUT_AB = 0, 1
+LAYOUT_AA, LAYOUT_AB, LAYOUT_AB2 = 0, 1, 2
 ANNULUS, CYLINDER = 0, 1
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
 NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC = 0, 1, 2, 3, 4, 5
 
 STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
-LAYOUT = {"aa": LAYOUT_AA, "ab": LAYOUT_AB}
+LAYOUT = {"aa": LAYOUT_AA, "ab": LAYOUT_AB, "ab2": LAYOUT_AB2}
 DERIV = {"lagged": 0, "current": 1}
 
 # Every symbol include/axlb.h declares.
@@ -175,7 +175,8 @@ class Lattice:
     """One lattice of the HIP library, set up from a case dict of
     ``paper_1806_10241_amd.inputs``.
 
-    storage: "f32" | "f16" | "bf16"; layout: "aa" (one buffer) | "ab".
+    storage: "f32" | "f16" | "bf16"; layout: "aa" (one buffer) | "ab" (two
+    buffers) | "ab2" (two buffers, two steps per launch).
     deriv: "lagged" (previous-step fields) | "current" (this step's output
     fields; needs layout "ab").
     stream: a ``torch.cuda.Stream`` to run on (None: the library's own).

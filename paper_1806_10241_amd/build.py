@@ -8,8 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaxlb.so")
-SOURCES = ["axlb_kernels.hip", "axlb_current.hip", "axlb_api.hip", "axlb_batch.hip",
-           "axlb_pool.cpp"]
+SOURCES = ["axlb_kernels.hip", "axlb_current.hip", "axlb_twostep.hip", "axlb_api.hip",
+           "axlb_batch.hip", "axlb_pool.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

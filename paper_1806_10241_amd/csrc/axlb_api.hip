@@ -34,7 +34,7 @@ Layout layout_for(int Nr, int Nz, int storage, int layout) {
     L.fld_bytes = up(5 * N * sizeof(double));
     L.snap_bytes = up(4 * N * sizeof(double));
     L.red_bytes = up((RED_BLOCKS * 9 + 16) * sizeof(double));
-    L.total = (layout == AXLB_LAYOUT_AB ? 2 : 1) * L.pop_bytes + 2 * L.lag_bytes + L.fld_bytes +
+    L.total = (layout == AXLB_LAYOUT_AA ? 1 : 2) * L.pop_bytes + 2 * L.lag_bytes + L.fld_bytes +
               L.snap_bytes + L.red_bytes;
     return L;
 }
@@ -118,33 +118,59 @@ static int check_bcs(axlb_lattice *L) {
     return AXLB_OK;
 }
 
-// The kernel launch of step t (counted from the lattice's creation): the
-// parity of t selects the AA phase, or which buffer is read, and which
-// lagged-field block is read and which written.
-static int launch_one(axlb_lattice *L, long t) {
+static bool two_buffers(const axlb_lattice *L) { return L->layout != AXLB_LAYOUT_AA; }
+
+// Launches step t (counted from the lattice's creation), or steps t and
+// t + 1 when `two` (the two-step layout only).  The AA phase follows the
+// parity of t; the two-buffer layouts read buffer `cur` (populations and
+// lagged fields) and write the other one.
+static int launch_steps(axlb_lattice *L, long t, int cur, bool two) {
     const KParams &P = L->P;
-    const int par = (int)(t & 1);
-    LagT *Mprev = L->lag[par], *Mnext = L->lag[par ^ 1];
     hipError_t e;
-    if (L->deriv == AXLB_DERIV_CURRENT)
-        e = launch_step_current(P, L->storage, L->tile, L->pop[par], L->pop[par ^ 1], L->stream);
-    else if (L->layout == AXLB_LAYOUT_AA)
-        e = launch_step(P, L->storage, L->tile, par == 0 ? 1 : 2, L->pop[0], L->pop[0], Mprev,
-                        Mnext, L->stream);
-    else
-        e = launch_step(P, L->storage, L->tile, 0, L->pop[par], L->pop[par ^ 1], Mprev, Mnext,
-                        L->stream);
+    if (L->layout == AXLB_LAYOUT_AA) {
+        const int par = (int)(t & 1);
+        e = launch_step(P, L->storage, L->tile, par == 0 ? 1 : 2, L->pop[0], L->pop[0], L->lag[par],
+                        L->lag[par ^ 1], L->stream);
+    } else if (L->deriv == AXLB_DERIV_CURRENT) {
+        e = launch_step_current(P, L->storage, L->tile, L->pop[cur], L->pop[cur ^ 1], L->stream);
+    } else if (two) {
+        e = launch_step_two(P, L->storage, L->pop[cur], L->pop[cur ^ 1], L->lag[cur],
+                            L->lag[cur ^ 1], L->stream);
+    } else {
+        e = launch_step(P, L->storage, L->tile, 0, L->pop[cur], L->pop[cur ^ 1], L->lag[cur],
+                        L->lag[cur ^ 1], L->stream);
+    }
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return AXLB_OK;
 }
 
-// HIP graph of BUNDLE consecutive steps starting at an even (k = 0) or odd
-// (k = 1) step count; BUNDLE is even, so every buffer role recurs.
+// One step as a plain launch, advancing the step count and the buffer.
+static int launch_one(axlb_lattice *L) {
+    const int rc = launch_steps(L, L->steps, L->cur, false);
+    if (rc) return rc;
+    L->steps += 1;
+    if (two_buffers(L)) L->cur ^= 1;
+    return AXLB_OK;
+}
+
+// Key of the graph that runs the next bundle: the AA phase, or the buffer
+// the two-buffer layouts read (a bundle flips it an even number of times).
+static int graph_key(const axlb_lattice *L) {
+    return two_buffers(L) ? L->cur : (int)(L->steps & 1);
+}
+
+// HIP graph of BUNDLE consecutive steps for graph key k (see graph_key);
+// BUNDLE is even (and a multiple of 4), so every buffer role recurs.
 static int ensure_graph(axlb_lattice *L, int k) {
     if (L->graph_exec[k]) return AXLB_OK;
     HIP_TRY(L, hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
     int rc = AXLB_OK;
-    for (long s = 0; s < BUNDLE && rc == AXLB_OK; ++s) rc = launch_one(L, k + s);
+    const bool two = L->layout == AXLB_LAYOUT_AB2;
+    int cur = k;
+    for (long s = 0; s < BUNDLE && rc == AXLB_OK; s += two ? 2 : 1) {
+        rc = launch_steps(L, k + s, cur, two);  // for AA, k + s has the parity of the step
+        cur ^= 1;
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(L->stream, &g);
     if (rc != AXLB_OK) {
@@ -177,16 +203,15 @@ static int set_device(axlb_lattice *L) {
 // Fields of the current state into L->fld (device, FP64 planes rho, u_r,
 // u_z, u_theta, T).
 static int compute_fields(axlb_lattice *L) {
-    const long t = L->steps;
-    const int par = (int)(t & 1);
+    const int par = (int)(L->steps & 1), cur = L->cur;
     hipError_t e;
     if (L->deriv == AXLB_DERIV_CURRENT)
-        e = launch_fields_current(L->P, L->storage, L->pop[par], L->fld, L->stream);
+        e = launch_fields_current(L->P, L->storage, L->pop[cur], L->fld, L->stream);
     else if (L->layout == AXLB_LAYOUT_AA)
         e = launch_fields(L->P, L->storage, par == 0 ? 1 : 2, L->pop[0], L->lag[par], L->fld,
                           L->stream);
     else
-        e = launch_fields(L->P, L->storage, 0, L->pop[par], L->lag[par], L->fld, L->stream);
+        e = launch_fields(L->P, L->storage, 0, L->pop[cur], L->lag[cur], L->fld, L->stream);
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("fields launch: ") + hipGetErrorString(e));
     return AXLB_OK;
 }
@@ -204,18 +229,15 @@ int axlb::lattice_start(axlb_lattice *L) {
 }
 
 int axlb::lattice_step_once(axlb_lattice *L) {
-    int rc = lattice_start(L);
+    const int rc = lattice_start(L);
     if (rc) return rc;
-    rc = launch_one(L, L->steps);
-    if (rc) return rc;
-    L->steps += 1;
-    return AXLB_OK;
+    return launch_one(L);
 }
 
 extern "C" {
 
 int axlb_state_bytes(int Nr, int Nz, int storage, int layout, size_t *bytes) {
-    if (!bytes || Nr < 2 || Nz < 1 || storage < 0 || storage > 2 || layout < 0 || layout > 1)
+    if (!bytes || Nr < 2 || Nz < 1 || storage < 0 || storage > 2 || layout < 0 || layout > 2)
         return fail(nullptr, AXLB_EINVAL, "axlb_state_bytes: bad arguments");
     *bytes = layout_for(Nr, Nz, storage, layout).total;
     return AXLB_OK;
@@ -251,11 +273,12 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     O.device = -1;
     if (opt) O = *opt;
     if (O.storage < 0 || O.storage > 2) return fail(nullptr, AXLB_EINVAL, "unknown storage");
-    if (O.layout < 0 || O.layout > 1) return fail(nullptr, AXLB_EINVAL, "unknown layout");
+    if (O.layout < 0 || O.layout > 2) return fail(nullptr, AXLB_EINVAL, "unknown layout");
     if (O.deriv != AXLB_DERIV_LAGGED && O.deriv != AXLB_DERIV_CURRENT)
         return fail(nullptr, AXLB_EINVAL, "unknown derivative time level");
     if (O.deriv == AXLB_DERIV_CURRENT && O.layout != AXLB_LAYOUT_AB)
-        return fail(nullptr, AXLB_EINVAL, "current-step derivatives need the two-buffer layout");
+        return fail(nullptr, AXLB_EINVAL,
+                    "current-step derivatives need the two-buffer, one-step layout");
     if (!std::isfinite(O.T_ref)) return fail(nullptr, AXLB_EINVAL, "T_ref must be finite");
 
     axlb_lattice *L = new (std::nothrow) axlb_lattice();
@@ -309,7 +332,7 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     char *p = L->base;
     L->pop[0] = p;
     p += L->lay.pop_bytes;
-    if (L->layout == AXLB_LAYOUT_AB) {
+    if (two_buffers(L)) {
         L->pop[1] = p;
         p += L->lay.pop_bytes;
     } else {
@@ -402,6 +425,7 @@ int axlb_set_fields(axlb_lattice *L, const double *rho, const double *ur, const 
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("init launch: ") + hipGetErrorString(e));
     HIP_TRY(L, hipStreamSynchronize(L->stream));
     L->steps = 0;
+    L->cur = 0;
     L->has_snap = false;
     return AXLB_OK;
 }
@@ -415,16 +439,21 @@ int axlb_step(axlb_lattice *L, long n) {
     if (rc) return rc;
     while (n > 0) {
         if (n >= BUNDLE && L->use_graphs) {
-            const int k = (int)(L->steps & 1);
+            const int k = graph_key(L);
             rc = ensure_graph(L, k);
             if (rc) return rc;
             HIP_TRY(L, hipGraphLaunch(L->graph_exec[k], L->stream));
             L->steps += BUNDLE;
             n -= BUNDLE;
-        } else {
-            rc = launch_one(L, L->steps);
+        } else if (n >= 2 && L->layout == AXLB_LAYOUT_AB2) {
+            rc = launch_steps(L, L->steps, L->cur, true);
             if (rc) return rc;
-            L->steps += 1;
+            L->steps += 2;
+            L->cur ^= 1;
+            n -= 2;
+        } else {
+            rc = launch_one(L);
+            if (rc) return rc;
             n -= 1;
         }
     }
@@ -559,13 +588,15 @@ int axlb_save(axlb_lattice *L, void *host, size_t bytes) {
     if (bytes < need) return fail(L, AXLB_EINVAL, "buffer too small");
     int rc = set_device(L);
     if (rc) return rc;
-    const int par = (int)(L->steps & 1);
+    // the buffers the next step reads: AA's one population buffer and the
+    // lagged block of the step parity; the two-buffer layouts' current pair
+    const int k = two_buffers(L) ? L->cur : (int)(L->steps & 1);
     Header h = {MAGIC, L->Nr, L->Nz, L->storage, L->layout, L->steps, L->lay.pop_bytes, L->lay.lag_bytes};
     char *p = (char *)host;
     std::memcpy(p, &h, sizeof(h));
-    void *pop = L->layout == AXLB_LAYOUT_AA ? L->pop[0] : L->pop[par];
+    void *pop = two_buffers(L) ? L->pop[k] : L->pop[0];
     HIP_TRY(L, hipMemcpyAsync(p + sizeof(h), pop, L->lay.pop_bytes, hipMemcpyDeviceToHost, L->stream));
-    HIP_TRY(L, hipMemcpyAsync(p + sizeof(h) + L->lay.pop_bytes, L->lag[par], L->lay.lag_bytes,
+    HIP_TRY(L, hipMemcpyAsync(p + sizeof(h) + L->lay.pop_bytes, L->lag[k], L->lay.lag_bytes,
                               hipMemcpyDeviceToHost, L->stream));
     HIP_TRY(L, hipStreamSynchronize(L->stream));
     return AXLB_OK;
@@ -585,11 +616,11 @@ int axlb_load(axlb_lattice *L, const void *host, size_t bytes) {
         return fail(L, AXLB_EINVAL, "image does not match this lattice");
     int rc = set_device(L);
     if (rc) return rc;
-    const int par = (int)(h.steps & 1);
+    const int k = two_buffers(L) ? L->cur : (int)(h.steps & 1);
     const char *p = (const char *)host;
-    void *pop = L->layout == AXLB_LAYOUT_AA ? L->pop[0] : L->pop[par];
+    void *pop = two_buffers(L) ? L->pop[k] : L->pop[0];
     HIP_TRY(L, hipMemcpyAsync(pop, p + sizeof(h), L->lay.pop_bytes, hipMemcpyHostToDevice, L->stream));
-    HIP_TRY(L, hipMemcpyAsync(L->lag[par], p + sizeof(h) + L->lay.pop_bytes, L->lay.lag_bytes,
+    HIP_TRY(L, hipMemcpyAsync(L->lag[k], p + sizeof(h) + L->lay.pop_bytes, L->lay.lag_bytes,
                               hipMemcpyHostToDevice, L->stream));
     HIP_TRY(L, hipStreamSynchronize(L->stream));
     L->steps = h.steps;
@@ -645,11 +676,12 @@ int axlb_autotune(axlb_lattice *L, int steps_per_trial, double *ms_per_step, int
     int rc = lattice_start(L);
     if (rc) return rc;
     // the trials step the lattice: keep the state and restore it afterwards
-    const size_t pops = (L->layout == AXLB_LAYOUT_AB ? 2 : 1) * L->lay.pop_bytes;
+    const size_t pops = (two_buffers(L) ? 2 : 1) * L->lay.pop_bytes;
     const size_t bytes = pops + 2 * L->lay.lag_bytes;
     char *keep = nullptr;
     if (hipMalloc((void **)&keep, bytes) != hipSuccess) return fail(L, AXLB_ENOMEM, "autotune snapshot");
     const long steps0 = L->steps;
+    const int cur0 = L->cur;
     const int tile0 = L->tile;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&]() {
@@ -668,9 +700,9 @@ int axlb_autotune(axlb_lattice *L, int steps_per_trial, double *ms_per_step, int
     for (int t = 0; t < tile_count(); ++t) {
         L->tile = t;
         int r2 = AXLB_OK;
-        for (int s = 0; s < 2 && r2 == AXLB_OK; ++s, ++L->steps) r2 = launch_one(L, L->steps);
+        for (int s = 0; s < 2 && r2 == AXLB_OK; ++s) r2 = launch_one(L);
         (void)hipEventRecord(e0, L->stream);
-        for (int s = 0; s < steps_per_trial && r2 == AXLB_OK; ++s, ++L->steps) r2 = launch_one(L, L->steps);
+        for (int s = 0; s < steps_per_trial && r2 == AXLB_OK; ++s) r2 = launch_one(L);
         (void)hipEventRecord(e1, L->stream);
         float ms = 0.f;
         if (r2 != AXLB_OK || hipEventSynchronize(e1) != hipSuccess ||
@@ -691,6 +723,7 @@ int axlb_autotune(axlb_lattice *L, int steps_per_trial, double *ms_per_step, int
     cleanup();
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, "autotune restore");
     L->steps = steps0;
+    L->cur = cur0;
     L->has_snap = false;
     if (best_tile != L->tile || L->tile != tile0) drop_graphs(L);
     L->tile = best_tile;

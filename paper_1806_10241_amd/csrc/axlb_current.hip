@@ -24,17 +24,6 @@ __device__ __forceinline__ void put_fields(float (&F)[4][H][W], int a, int b, co
     F[3][a][b] = m.dphi;
 }
 
-// The LDS tile as a field source for differences(): (ta, tb) is the node's
-// cell; periodic images sit in the cells beyond the domain.
-template <int H, int W>
-struct TileSource {
-    const float (&F)[4][H][W];
-    int ta, tb;
-    __device__ __forceinline__ float operator()(int v, int di, int dj) const {
-        return F[v][ta + di][tb + dj];
-    }
-};
-
 // Streams node (i, j) of src (or its periodic image along z) into the LDS
 // cell (a, b); positions outside the fluid that are not a periodic image are
 // left alone (their ghosts come from the wall and axis rules).

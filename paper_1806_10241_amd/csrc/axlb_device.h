@@ -47,6 +47,11 @@ __device__ __forceinline__ void lag_st(LagT *M, int v, long long plane, I off, f
     if (v == 3) lag_T(M, plane)[off] = x;
     else M[v * plane + off] = __float2half_rn(x * LAG_SCALE);
 }
+// The value lag_ld returns after lag_st stored x in field v.
+__device__ __forceinline__ float lag_round(int v, float x) {
+    if (v == 3) return x;
+    return __half2float(__float2half_rn(x * LAG_SCALE)) * (1.f / LAG_SCALE);
+}
 
 // Everything a step kernel needs, passed by value.
 struct KParams {

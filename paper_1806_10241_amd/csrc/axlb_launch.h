@@ -28,6 +28,10 @@ hipError_t launch_step_current(const KParams &P, int storage, int tile, const vo
                                void *dst, hipStream_t st);
 hipError_t launch_fields_current(const KParams &P, int storage, const void *src, double *out,
                                  hipStream_t st);
+// Two steps in one launch (two buffers, lagged derivatives): src/Mprev hold
+// the state before step t, dst/Mnext receive it after step t + 1.
+hipError_t launch_step_two(const KParams &P, int storage, const void *src, void *dst,
+                           const LagT *Mprev, LagT *Mnext, hipStream_t st);
 hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
                        LagT *M, hipStream_t st);
 hipError_t launch_residual(const double *fld, const double *snap, long long N, double *part,

@@ -64,18 +64,34 @@ __device__ __forceinline__ float wall_value(const KParams &P, int face, float ym
 }
 
 // ----------------------------------------------------------------------------
+// Population sources for the pulls: src(p, i, j) is the value in plane p
+// (0..18) at node (i, j), where i may lie one row beyond a periodic z face
+// (the source then supplies the periodic image).  GlobalPops reads a
+// population buffer in device memory.
+template <class S>
+struct GlobalPops {
+    const KParams &P;
+    const S *A;
+    __device__ __forceinline__ float operator()(int p, int i, int j) const {
+        if (i < 0) i += P.Nz;
+        else if (i >= P.Nz) i -= P.Nz;
+        return Conv<S>::ld(A + p * P.plane + (long long)i * P.pitch + j);
+    }
+};
+
 // Pull of population Q of distribution FLD into node (i, j) when the source
 // node (i - e_x, j - e_y) lies outside the fluid.  Precedence per link: a
 // solid wall (radial faces first) -> half-way bounce-back for f and for zero
 // flux, anti-bounce-back -v + 2 w s_w (w = 1/6) for an imposed u_theta or T;
 // then the axis -> specular reflection from the node shifted by e_x, with a
-// sign change for g (u_theta is odd); then the periodic wrap along z.
+// sign change for g (u_theta is odd); then the periodic image along z.
 // AA selects the slot convention of the odd phase of the in-place layout.
-template <class S, bool AA, int FLD, int Q>
-__device__ __forceinline__ float pull_edge(const KParams &P, const S *A, int i, int j) {
+template <bool AA, int FLD, int Q, class Src>
+__device__ __forceinline__ float pull_edge(const KParams &P, const Src &src, int i, int j) {
     using L = Lat<FLD>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
-    int si = i - ex, sj = j - ey;
+    const int si = i - ex;
+    int sj = j - ey;
     const int fy = sj < 0 ? R_IN : (sj >= P.Nr ? R_OUT : -1);
     const int fx = si < 0 ? Z_LO : (si >= P.Nz ? Z_HI : -1);
     int wall = -1;
@@ -85,7 +101,7 @@ __device__ __forceinline__ float pull_edge(const KParams &P, const S *A, int i, 
         // f*_{opp Q}(i, j): AB keeps it in plane opp Q, the even AA phase put
         // it into plane Q.
         constexpr int slot = AA ? Q : L::opp(Q);
-        const float v = Conv<S>::ld(A + (L::OFF + slot) * P.plane + (long long)i * P.pitch + j);
+        const float v = src(L::OFF + slot, i, j);
         if (FLD == FLOW || kind_of(P, wall, FLD) == ADIABATIC) return v;
         const float ym = P.r0 + (float)j + 0.5f - 0.5f * (float)ey;
         return -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
@@ -97,21 +113,46 @@ __device__ __forceinline__ float pull_edge(const KParams &P, const S *A, int i, 
         sj = j;
         if (FLD == SWIRL) sign = -1.f;
     }
-    if (fx >= 0) si += si < 0 ? P.Nz : -P.Nz;  // periodic
     const int slot = AA ? L::opp(qs) : qs;
-    return sign * Conv<S>::ld(A + (L::OFF + slot) * P.plane + (long long)si * P.pitch + sj);
+    return sign * src(L::OFF + slot, si, sj);  // a z row beyond a periodic face: its image
 }
 
-template <class S, bool AA, int FLD, int Q>
-__device__ __forceinline__ float pull(const KParams &P, const S *A, int i, int j) {
+template <bool AA, int FLD, int Q, class Src>
+__device__ __forceinline__ float pull(const KParams &P, const Src &src, int i, int j) {
     using L = Lat<FLD>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
     const int si = i - ex, sj = j - ey;
     if ((unsigned)si < (unsigned)P.Nz && (unsigned)sj < (unsigned)P.Nr) {
         constexpr int slot = AA ? L::opp(Q) : Q;
-        return Conv<S>::ld(A + (L::OFF + slot) * P.plane + (long long)si * P.pitch + sj);
+        return src(L::OFF + slot, si, sj);
     }
-    return pull_edge<S, AA, FLD, Q>(P, A, i, j);
+    return pull_edge<AA, FLD, Q>(P, src, i, j);
+}
+
+// All 19 pulls of node (i, j) from a population source, with the boundary
+// rules wherever a source node lies outside the fluid.
+template <bool AA, class Src>
+__device__ __forceinline__ void pull_all(const KParams &P, const Src &src, int i, int j,
+                                         float (&f)[9], float (&g)[5], float (&h)[5]) {
+    f[0] = pull<AA, FLOW, 0>(P, src, i, j);
+    f[1] = pull<AA, FLOW, 1>(P, src, i, j);
+    f[2] = pull<AA, FLOW, 2>(P, src, i, j);
+    f[3] = pull<AA, FLOW, 3>(P, src, i, j);
+    f[4] = pull<AA, FLOW, 4>(P, src, i, j);
+    f[5] = pull<AA, FLOW, 5>(P, src, i, j);
+    f[6] = pull<AA, FLOW, 6>(P, src, i, j);
+    f[7] = pull<AA, FLOW, 7>(P, src, i, j);
+    f[8] = pull<AA, FLOW, 8>(P, src, i, j);
+    g[0] = pull<AA, SWIRL, 0>(P, src, i, j);
+    g[1] = pull<AA, SWIRL, 1>(P, src, i, j);
+    g[2] = pull<AA, SWIRL, 2>(P, src, i, j);
+    g[3] = pull<AA, SWIRL, 3>(P, src, i, j);
+    g[4] = pull<AA, SWIRL, 4>(P, src, i, j);
+    h[0] = pull<AA, THERMAL, 0>(P, src, i, j);
+    h[1] = pull<AA, THERMAL, 1>(P, src, i, j);
+    h[2] = pull<AA, THERMAL, 2>(P, src, i, j);
+    h[3] = pull<AA, THERMAL, 3>(P, src, i, j);
+    h[4] = pull<AA, THERMAL, 4>(P, src, i, j);
 }
 
 // Odd AA phase: post-collision f*_Q(i, j) = v goes to the slot from which
@@ -199,6 +240,17 @@ __device__ __forceinline__ void differences(const KParams &P, const Get &get, in
     d[3] = 0.5f * (field_at(P, get, 2, i, j, 0, +1) - field_at(P, get, 2, i, j, 0, -1));
     d[4] = 0.5f * (field_at(P, get, 3, i, j, 0, +1) - field_at(P, get, 3, i, j, 0, -1));
 }
+
+// An LDS tile of the four derivative fields as a field source: (ta, tb) is
+// the node's cell; periodic images sit in the cells beyond the domain.
+template <int H, int W>
+struct TileSource {
+    const float (&F)[4][H][W];
+    int ta, tb;
+    __device__ __forceinline__ float operator()(int v, int di, int dj) const {
+        return F[v][ta + di][tb + dj];
+    }
+};
 
 // The lagged fields of the previous step as a field source (periodic
 // images wrap along z).
@@ -456,25 +508,7 @@ __device__ __forceinline__ void gather(const KParams &P, const S *A, int i, int 
         h[4] = pull_in<S, AA, THERMAL, 4>(P, A, n);
         return;
     }
-    f[0] = pull<S, AA, FLOW, 0>(P, A, i, j);
-    f[1] = pull<S, AA, FLOW, 1>(P, A, i, j);
-    f[2] = pull<S, AA, FLOW, 2>(P, A, i, j);
-    f[3] = pull<S, AA, FLOW, 3>(P, A, i, j);
-    f[4] = pull<S, AA, FLOW, 4>(P, A, i, j);
-    f[5] = pull<S, AA, FLOW, 5>(P, A, i, j);
-    f[6] = pull<S, AA, FLOW, 6>(P, A, i, j);
-    f[7] = pull<S, AA, FLOW, 7>(P, A, i, j);
-    f[8] = pull<S, AA, FLOW, 8>(P, A, i, j);
-    g[0] = pull<S, AA, SWIRL, 0>(P, A, i, j);
-    g[1] = pull<S, AA, SWIRL, 1>(P, A, i, j);
-    g[2] = pull<S, AA, SWIRL, 2>(P, A, i, j);
-    g[3] = pull<S, AA, SWIRL, 3>(P, A, i, j);
-    g[4] = pull<S, AA, SWIRL, 4>(P, A, i, j);
-    h[0] = pull<S, AA, THERMAL, 0>(P, A, i, j);
-    h[1] = pull<S, AA, THERMAL, 1>(P, A, i, j);
-    h[2] = pull<S, AA, THERMAL, 2>(P, A, i, j);
-    h[3] = pull<S, AA, THERMAL, 3>(P, A, i, j);
-    h[4] = pull<S, AA, THERMAL, 4>(P, A, i, j);
+    pull_all<AA>(P, GlobalPops<S>{P, A}, i, j, f, g, h);
 }
 
 template <class S, int MODE>
@@ -579,6 +613,21 @@ __device__ __forceinline__ void edge_node(const KParams &P, int e, int &i, int &
 // source step, cascaded collisions with the source moments, store; the
 // node's half-step fields go to the lagged buffer of the next step.
 // `interior` must equal interior_node(P, i, j); callers pass a constant.
+// Output moments, half source step and the three collisions of a node in
+// row j whose pulled populations are f, g, h and whose central differences
+// are d; f, g, h become the post-collision populations, and the half-step
+// state (the node's lagged fields) is returned.
+__device__ __forceinline__ Half relax_node(const KParams &P, int j, float (&f)[9], float (&g)[5],
+                                           float (&h)[5], const float d[5]) {
+    const Moments m = moments(f, g, h);
+    const float iy = rcp(P.r0 + (float)j + 0.5f);
+    const Half H = half_step(P, iy, m.drho, m.jx, m.jy, m.psi, m.dphi, d);
+    collide_f(P, f, H);
+    collide_adv(g, H.ux, H.uy, H.psi, H.psi, H.hSpsi, P.og12, P.og3, P.og4);
+    collide_adv(h, H.ux, H.uy, P.Tref + H.dphi, H.dphi, H.hSphi, P.oh12, P.oh3, P.oh4);
+    return H;
+}
+
 template <class S, int MODE>
 __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *dst,
                                             const LagT *__restrict__ Mprev,
@@ -586,14 +635,9 @@ __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *d
                                             bool interior) {
     float f[9], g[5], h[5];
     gather<S, MODE>(P, src, i, j, interior, f, g, h);
-    const Moments m = moments(f, g, h);
     float d[5];
     derivatives(P, Mprev, i, j, interior, d);
-    const float iy = rcp(P.r0 + (float)j + 0.5f);
-    const Half H = half_step(P, iy, m.drho, m.jx, m.jy, m.psi, m.dphi, d);
-    collide_f(P, f, H);
-    collide_adv(g, H.ux, H.uy, H.psi, H.psi, H.hSpsi, P.og12, P.og3, P.og4);
-    collide_adv(h, H.ux, H.uy, P.Tref + H.dphi, H.dphi, H.hSphi, P.oh12, P.oh3, P.oh4);
+    const Half H = relax_node(P, j, f, g, h, d);
     scatter<S, MODE>(P, dst, i, j, interior, f, g, h);
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
     lag_st(Mnext, 0, P.plane, n, H.ux);

@@ -233,3 +233,38 @@ def test_autotune_restores_the_state(gpu):
     b = axlb.Lattice(c)
     b.step(57)
     assert a.save() == b.save()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_two_step_launches_equal_single_steps_bitwise(gpu, name, storage):
+    """Two steps per launch (tile and ring in LDS) against one step per
+    launch on the same two buffers: 250 steps (two graph bundles, then 25
+    two-step launches) and 301 (an odd step at the end)."""
+    say("two-step launches", name, storage)
+    from paper_1806_10241_amd import axlb
+    c = CASES[name]()
+    for steps in (250, 301):
+        a = axlb.Lattice(c, storage=storage, layout="ab2")
+        b = axlb.Lattice(c, storage=storage, layout="ab")
+        for n in (steps, 2):  # the extra steps read the lagged fields left behind
+            a.step(n)
+            b.step(n)
+            fa, fb = a.fields(), b.fields()
+            for k in FIELDS:
+                assert np.array_equal(fa[k], fb[k]), (steps, n, k)
+
+
+def test_two_step_checkpoint_and_single_launches(gpu):
+    say("two-step checkpoint")
+    from paper_1806_10241_amd import axlb
+    c = c3_case()
+    a = axlb.Lattice(c, layout="ab2")
+    a.step(123)
+    img = a.save()
+    a.step(77)
+    b = axlb.Lattice(c, layout="ab2", init_fields=False)
+    b.load(img)
+    for _ in range(77):
+        b.step(1)
+    assert a.save() == b.save()
