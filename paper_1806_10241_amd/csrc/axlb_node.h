@@ -579,9 +579,11 @@ __device__ __forceinline__ void scatter(const KParams &P, S *A, int i, int j, bo
 }
 
 // A node whose eight neighbours are all fluid nodes: no boundary rule can
-// apply to any of its links or derivative stencils.
+// apply to any of its links or derivative stencils.  False for every (i, j)
+// outside the lattice, also when Nz or Nr is below 3 (the tile kernels of
+// the odd phase rely on that to skip the ragged tail).
 __device__ __forceinline__ bool interior_node(const KParams &P, int i, int j) {
-    return (unsigned)(i - 1) < (unsigned)(P.Nz - 2) && (unsigned)(j - 1) < (unsigned)(P.Nr - 2);
+    return i >= 1 && i <= P.Nz - 2 && j >= 1 && j <= P.Nr - 2;
 }
 
 // The nodes on the edge of a lattice, where boundary rules may apply:

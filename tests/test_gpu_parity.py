@@ -268,3 +268,25 @@ def test_two_step_checkpoint_and_single_launches(gpu):
     for _ in range(77):
         b.step(1)
     assert a.save() == b.save()
+
+
+@pytest.mark.parametrize("shape", [(2, 1), (3, 2), (2, 5), (65, 1)])
+def test_degenerate_lattices_match_the_oracle(gpu, orc, shape):
+    """Lattices with one or two rows or columns (every node an edge node;
+    one periodic row), driven by a turning, heated inner wall and an axial
+    body force: every layout against the oracle after 400 steps."""
+    Nr, Nz = shape
+    say("degenerate lattice", Nr, Nz)
+    from paper_1806_10241_amd import axlb
+    c = I.couette_poiseuille_conduction(Nr=Nr, Nz=Nz, r_inner=5.0, u_wall=0.01, g=1e-4)
+    if Nz >= 2:  # walls along z as well
+        for fld, kind in ((I.FLOW, I.NOSLIP), (I.SWIRL, I.NOSLIP), (I.THERMAL, I.ADIABATIC)):
+            c["bc"][(I.Z_LO, fld)] = (kind, 0.0)
+            c["bc"][(I.Z_HI, fld)] = (kind, 0.0)
+    ref = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
+    ref.step(400)
+    want = ref.fields()
+    for layout in ("aa", "ab", "ab2"):
+        lat = axlb.Lattice(c, layout=layout)
+        lat.step(400)
+        assert_parity(lat.fields(), want, TOL["f32"], (shape, layout), TOL_DRHO["f32"])
