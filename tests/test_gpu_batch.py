@@ -104,3 +104,23 @@ def test_batched_workload_members_match_oracle(gpu, orc):
             f: "%.2e" % e for f, (e, _) in field_errors(got, want).items()}))
         assert_parity(got, want, TOL["f32"], "member %d" % k, TOL_DRHO["f32"])
     b.close()
+
+
+def test_batch_with_degenerate_members_equals_alone(gpu):
+    """Members with one or two rows or columns next to ordinary ones."""
+    say("batch with degenerate members")
+    from paper_1806_10241_amd import axlb
+    cases = [I.couette_poiseuille_conduction(Nr=65, Nz=1, r_inner=5.0),
+             I.couette_poiseuille_conduction(Nr=2, Nz=3, r_inner=5.0),
+             I.rotating_lid_cylinder(Nr=3, Nz=2, Re=50.0, Ri=0.5),
+             I.annulus_convection(Nr=70, Nz=66, Ra=1e4, seed=81)]
+    alone = [axlb.Lattice(c) for c in cases]
+    batched = [axlb.Lattice(c) for c in cases]
+    b = axlb.Batch(batched)
+    b.step(150)
+    b.sync()
+    for lat in alone:
+        lat.step(150)
+    for la, lb in zip(alone, batched):
+        assert la.save() == lb.save()
+    b.close()

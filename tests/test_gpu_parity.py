@@ -290,3 +290,30 @@ def test_degenerate_lattices_match_the_oracle(gpu, orc, shape):
         lat = axlb.Lattice(c, layout=layout)
         lat.step(400)
         assert_parity(lat.fields(), want, TOL["f32"], (shape, layout), TOL_DRHO["f32"])
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (3, 1), (66, 2)])
+def test_degenerate_cylinders_match_the_oracle(gpu, orc, shape):
+    """A cylinder with the axis rule and one or two rows or columns: a
+    rotating, heated lid over a short cylinder (two rows), or a periodic
+    pipe with a turning wall (one row)."""
+    Nr, Nz = shape
+    say("degenerate cylinder", Nr, Nz)
+    from paper_1806_10241_amd import axlb
+    if Nz == 1:
+        c = I.rotating_lid_cylinder(Nr=Nr, Nz=Nz, Re=50.0, Ri=0.0)
+        for fld in (I.FLOW, I.SWIRL, I.THERMAL):
+            c["bc"][(I.Z_LO, fld)] = (I.PERIODIC, 0.0)
+            c["bc"][(I.Z_HI, fld)] = (I.PERIODIC, 0.0)
+        c["bc"][(I.R_OUT, I.SWIRL)] = (I.OMEGA_R, c["Omega"])
+        c["bc"][(I.R_OUT, I.THERMAL)] = (I.DIRICHLET, 1.0)
+        c["g_axial"] = 1e-5
+    else:
+        c = I.rotating_lid_cylinder(Nr=Nr, Nz=Nz, Re=50.0, Ri=0.5)
+    ref = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
+    ref.step(300)
+    want = ref.fields()
+    for layout in ("aa", "ab", "ab2"):
+        lat = axlb.Lattice(c, layout=layout)
+        lat.step(300)
+        assert_parity(lat.fields(), want, TOL["f32"], (shape, layout), TOL_DRHO["f32"])
