@@ -196,7 +196,8 @@ def main():
                     help="time level of the source-term derivatives (current needs --layout ab)")
     ap.add_argument("--Nr", type=int, default=1024)
     ap.add_argument("--Nz", type=int, default=2048)
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=30,
+                    help="steps of the oracle on the benchmark lattice (~15 s on one core)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="step-kernel tile shape; -1: autotune on the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
