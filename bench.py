@@ -122,7 +122,8 @@ def bench_batched(n, steps, warmup, baseline_steps):
             "speedup_vs_loop": round(mlups / mlups_loop, 2), "nonfinite_instances": nonfinite}
 
 
-def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, order, window):
+def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, order, window,
+                 baseline=True):
     """Poisson arrivals of mixed solve requests (seeded trace) served by the
     continuous-batching pool, against serving the same trace one request at
     a time with plain single-lattice runs.  Latency = arrival to result."""
@@ -156,6 +157,15 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, 
     _, node_updates = pool.usage()
     lat_s = np.array([done[r] - arrival[r] for r in arrival])
     pool.close()
+    out = {"requests": n, "rate_per_s": rate, "tol": tol, "max_steps": max_steps,
+           "budget_gib": budget_gib, "admission": order, "node_window": window,
+           "grid": "Nr 64..%d x Nz 64..%d" % (2 ** max_nr_log2, 2 ** max_nz_log2),
+           "p50_s": round(float(np.percentile(lat_s, 50)), 4),
+           "p99_s": round(float(np.percentile(lat_s, 99)), 4),
+           "solves_per_s": round(n / makespan, 3),
+           "aggregate_mlups": round(node_updates / makespan / 1e6, 1)}
+    if not baseline:
+        return out
     # one request at a time: each case alone, same stop rule, FIFO queue
     finish = 0.0
     lat1 = []
@@ -172,17 +182,10 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, 
         finish = max(finish, at) + service
         lat1.append(finish - at)
     lat1 = np.array(lat1)
-    makespan1 = finish
-    return {"requests": n, "rate_per_s": rate, "tol": tol, "max_steps": max_steps,
-            "budget_gib": budget_gib, "admission": order, "node_window": window,
-            "grid": "Nr 64..%d x Nz 64..%d" % (2 ** max_nr_log2, 2 ** max_nz_log2),
-            "p50_s": round(float(np.percentile(lat_s, 50)), 4),
-            "p99_s": round(float(np.percentile(lat_s, 99)), 4),
-            "solves_per_s": round(n / makespan, 3),
-            "aggregate_mlups": round(node_updates / makespan / 1e6, 1),
-            "one_at_a_time": {"p50_s": round(float(np.percentile(lat1, 50)), 4),
-                              "p99_s": round(float(np.percentile(lat1, 99)), 4),
-                              "solves_per_s": round(n / makespan1, 3)}}
+    out["one_at_a_time"] = {"p50_s": round(float(np.percentile(lat1, 50)), 4),
+                            "p99_s": round(float(np.percentile(lat1, 99)), 4),
+                            "solves_per_s": round(n / finish, 3)}
+    return out
 
 
 def main():
@@ -212,9 +215,11 @@ def main():
     ap.add_argument("--serve-max-nr-log2", type=float, default=10.0)
     ap.add_argument("--serve-max-nz-log2", type=float, default=11.0)
     ap.add_argument("--serve-order", default="smallest", choices=["smallest", "fifo"])
-    ap.add_argument("--serve-window", type=int, default=4 << 20,
+    ap.add_argument("--serve-window", type=int, default=2 << 20,
                     help="cap on resident fluid nodes in the pool (0: none)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-no-baseline", action="store_true",
+                    help="skip serving the trace one request at a time")
     ap.add_argument("--single-launches", action="store_true",
                     help="one kernel launch per step instead of 100-step graphs")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -315,7 +320,8 @@ def main():
         out["served"] = bench_served(args.serve_n, args.serve_rate, args.serve_tol,
                                      args.serve_max_steps, args.serve_budget_gib,
                                      args.serve_max_nr_log2, args.serve_max_nz_log2,
-                                     args.serve_order, args.serve_window)
+                                     args.serve_order, args.serve_window,
+                                     baseline=not args.serve_no_baseline)
     if not args.no_cpu_baseline:
         print("bench: oracle CPU baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -46,8 +46,11 @@ extern "C" {
 
 /* ---- population storage (Section 2; FP32 arithmetic in every case) ---- */
 #define AXLB_F32 0   /* 4 bytes per population, 152 B per node update         */
-#define AXLB_F16 1   /* IEEE binary16, round to nearest even, 76 B per update  */
-#define AXLB_BF16 2  /* bfloat16, round to nearest even, 76 B per update       */
+#define AXLB_F16 1   /* IEEE binary16 of the value times 2^8, stochastic
+                        rounding, 76 B per node update                         */
+#define AXLB_BF16 2  /* bfloat16, stochastic rounding, 76 B per node update    */
+/* Stochastic rounding draws its random bits from a hash of the value and
+ * the slot, so that a run (and a checkpoint replay) is deterministic. */
 
 /* ---- streaming layouts ---- */
 #define AXLB_LAYOUT_AA 0 /* one population buffer, in place, alternating phases */
@@ -144,8 +147,8 @@ int axlb_state_bytes(int Nr, int Nz, int storage, int layout, size_t *bytes);
  *  Omega   angular velocity of OMEGA_R faces set with value NaN.
  *  w       relaxation rates (NULL: defaults); opt: storage/layout/stream/
  *          derivative time level (NULL: FP32, AA, T_ref = 0.5, own stream,
- *          current device, lagged); AXLB_EINVAL for CURRENT with the AA
- *          layout.
+ *          current device, lagged); AXLB_EINVAL for CURRENT with any
+ *          layout but AXLB_LAYOUT_AB.
  * Defaults: every face a no-slip wall with u_theta = 0 and zero heat flux;
  * a cylinder's inner face is the axis.  *out receives the handle. */
 int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, double alpha,
@@ -204,7 +207,9 @@ int axlb_load(axlb_lattice *lat, const void *host, size_t bytes);
  * nodes.  axlb_set_tile selects one for a lattice (results do not depend on
  * it); axlb_autotune times every shape for steps_per_trial steps on the
  * lattice itself, restores the state it found, selects the fastest, and
- * returns the per-step times in ms_per_step[AXLB_NTILES] (may be NULL). */
+ * returns the per-step times in ms_per_step[AXLB_NTILES] (may be NULL).
+ * The two-step launches of AXLB_LAYOUT_AB2 use a fixed 64 x 8 tile; the
+ * selected shape applies to its single steps. */
 #define AXLB_NTILES 8
 int axlb_tile_shape(int tile, int *tile_r, int *tile_z);
 int axlb_set_tile(axlb_lattice *lat, int tile);
