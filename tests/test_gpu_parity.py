@@ -206,6 +206,26 @@ def test_full_size_parity_in_bench_configuration(gpu, orc):
         assert np.linalg.norm(dg - dr) <= 1e-3 * np.linalg.norm(dr), k
 
 
+def test_full_size_bench_launches_equal_checked_launches(gpu):
+    """The benchmark's launch configuration at 1024 x 2048 (autotuned tile,
+    100-step graph bundles) gives the state of plain single launches with
+    the default tile, which the test above checks against the oracle."""
+    say("full size bench launch configuration")
+    from paper_1806_10241_amd import axlb
+    c = I.rotating_lid_cylinder(Nr=1024, Nz=2048)
+    init = smooth_fields(c["Nz"], c["Nr"], 7)
+    a = axlb.Lattice(c, init_fields=False)
+    a.set_fields(**init)
+    best, _ = a.autotune(steps_per_trial=10)
+    a.step(200)
+    b = axlb.Lattice(c, init_fields=False)
+    b.set_fields(**init)
+    for _ in range(200):
+        b.step(1)
+    say("  tile", axlb.tile_shape(best))
+    assert a.save() == b.save()
+
+
 def test_every_tile_shape_gives_identical_results(gpu):
     """The tile shape changes only which thread updates which node."""
     say("tile shapes")
