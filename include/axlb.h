@@ -96,6 +96,9 @@ extern "C" {
 #define AXLB_OMEGA_R 4   /* g: u_theta = Omega * r at the wall, Omega = value (NaN: the
                             lattice's Omega)                                            */
 #define AXLB_ADIABATIC 5 /* h (or g): zero normal flux                                  */
+#define AXLB_HALO 6      /* z faces only, all fields, AXLB_LAYOUT_AB with lagged derivatives:
+                            the neighbours beyond the face are the boundary row of an
+                            adjacent slab, imported with axlb_halo_import (below)        */
 
 typedef struct axlb_lattice axlb_lattice;
 
@@ -217,6 +220,22 @@ int axlb_get_tile(const axlb_lattice *lat, int *tile, int *tile_r, int *tile_z);
 int axlb_autotune(axlb_lattice *lat, int steps_per_trial, double *ms_per_step, int *best);
 
 void axlb_destroy(axlb_lattice *lat);
+
+/* ---- slabs of one lattice (a lattice cut along z, one piece per GPU) ----
+ * A slab's cut faces have kind AXLB_HALO.  Before each step, the row of
+ * each neighbouring slab next to the cut (its populations and lagged
+ * fields, as they stand before that step) must sit in the slab's halo of
+ * that face: axlb_halo_export packs a slab's boundary row next to `face`
+ * into axlb_halo_bytes bytes of device memory, the caller moves them (a
+ * copy on one device, a send and receive between devices) and
+ * axlb_halo_import copies them into the neighbour's halo of the facing
+ * face.  Steps then reproduce the uncut lattice bit for bit.  Both calls
+ * are asynchronous on the lattice's stream; the caller orders the copies
+ * between lattices (synchronise, or wait on events).  AXLB_EINVAL for a
+ * face other than Z_LO/Z_HI, NULL pointers or a layout other than AB. */
+int axlb_halo_bytes(const axlb_lattice *lat, size_t *bytes);
+int axlb_halo_export(axlb_lattice *lat, int face, void *device_dst);
+int axlb_halo_import(axlb_lattice *lat, int face, const void *device_src);
 
 /* ---- batches of independent lattices (uneven sizes) ----
  * A batch advances all its member lattices together: a step of many members

@@ -23,7 +23,7 @@ LAYOUT_AA, LAYOUT_AB, LAYOUT_AB2 = 0, 1, 2
 ANNULUS, CYLINDER = 0, 1
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
-NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC = 0, 1, 2, 3, 4, 5
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, HALO = 0, 1, 2, 3, 4, 5, 6
 
 STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
 LAYOUT = {"aa": LAYOUT_AA, "ab": LAYOUT_AB, "ab2": LAYOUT_AB2}
@@ -38,6 +38,7 @@ EXPORTS = [
     "axlb_autotune", "axlb_batch_create", "axlb_batch_size", "axlb_batch_step",
     "axlb_batch_sync", "axlb_batch_set_schedule", "axlb_batch_get_schedule",
     "axlb_batch_autotune", "axlb_batch_destroy", "axlb_batch_last_error", "axlb_step_each",
+    "axlb_halo_bytes", "axlb_halo_export", "axlb_halo_import",
     "axlb_pool_create", "axlb_pool_set_policy", "axlb_pool_submit", "axlb_pool_tick",
     "axlb_pool_status",
     "axlb_pool_result", "axlb_pool_usage", "axlb_pool_destroy", "axlb_pool_last_error",
@@ -130,6 +131,9 @@ def load():
         "axlb_batch_destroy": ([_vp], None),
         "axlb_batch_last_error": ([_vp], C.c_char_p),
         "axlb_step_each": ([C.POINTER(_vp), C.c_int, C.c_long], C.c_int),
+        "axlb_halo_bytes": ([_vp, C.POINTER(C.c_size_t)], C.c_int),
+        "axlb_halo_export": ([_vp, C.c_int, _vp], C.c_int),
+        "axlb_halo_import": ([_vp, C.c_int, _vp], C.c_int),
         "axlb_pool_create": ([C.c_size_t, C.c_int, C.c_int, C.POINTER(_vp)], C.c_int),
         "axlb_pool_set_policy": ([_vp, C.c_int, C.c_longlong], C.c_int),
         "axlb_pool_submit": ([_vp, C.POINTER(Request), C.POINTER(C.c_long)], C.c_int),
@@ -275,6 +279,19 @@ class Lattice:
         r = C.c_double()
         self._check(self._lib.axlb_residual(self._h, C.byref(r)))
         return r.value
+
+    def halo_bytes(self) -> int:
+        n = C.c_size_t()
+        self._check(self._lib.axlb_halo_bytes(self._h, C.byref(n)))
+        return n.value
+
+    def halo_export(self, face: int, device_ptr: int):
+        """Packs the boundary row next to z face `face` into device memory."""
+        self._check(self._lib.axlb_halo_export(self._h, int(face), _vp(device_ptr)))
+
+    def halo_import(self, face: int, device_ptr: int):
+        """Copies a packed neighbour row into the halo of z face `face`."""
+        self._check(self._lib.axlb_halo_import(self._h, int(face), _vp(device_ptr)))
 
     def save(self) -> bytes:
         n = C.c_size_t()

@@ -34,8 +34,10 @@ Layout layout_for(int Nr, int Nz, int storage, int layout) {
     L.fld_bytes = up(5 * N * sizeof(double));
     L.snap_bytes = up(4 * N * sizeof(double));
     L.red_bytes = up((RED_BLOCKS * 9 + 16) * sizeof(double));
+    L.halo_pop_bytes = up((size_t)NPOP * L.pitch * storage_size(storage));
+    L.halo_lag_bytes = up(LAG_NODE_BYTES * L.pitch);
     L.total = (layout == AXLB_LAYOUT_AA ? 1 : 2) * L.pop_bytes + 2 * L.lag_bytes + L.fld_bytes +
-              L.snap_bytes + L.red_bytes;
+              L.snap_bytes + L.red_bytes + 2 * (L.halo_pop_bytes + L.halo_lag_bytes);
     return L;
 }
 
@@ -95,6 +97,10 @@ KParams axlb::make_params(const axlb_lattice *L) {
             if (L->kind[f][d] == AXLB_OMEGA_R && std::isnan(v)) v = L->Omega;
             P.val[f][d] = (float)v;
         }
+    for (int f = 0; f < 2; ++f) {
+        P.halo_pop[f] = L->halo[f];
+        P.halo_lag[f] = (const LagT *)(L->halo[f] + L->lay.halo_pop_bytes);
+    }
     return P;
 }
 
@@ -104,17 +110,24 @@ static int check_bcs(axlb_lattice *L) {
         const bool plo = L->kind[AXLB_Z_LO][d] == AXLB_PERIODIC;
         const bool phi = L->kind[AXLB_Z_HI][d] == AXLB_PERIODIC;
         if (plo != phi) return fail(L, AXLB_EINVAL, "periodic z must be set on both z faces");
-        if (!plo && L->Nz < 2) return fail(L, AXLB_EINVAL, "Nz >= 2 needed with walls along z");
+        const bool wall = is_wall(L->kind[AXLB_Z_LO][d]) || is_wall(L->kind[AXLB_Z_HI][d]);
+        if (wall && L->Nz < 2) return fail(L, AXLB_EINVAL, "Nz >= 2 needed with walls along z");
     }
+    bool halo = false;
     for (int f = 0; f < 4; ++f) {
         const bool w = is_wall(L->kind[f][0]);
         const bool p = L->kind[f][0] == AXLB_PERIODIC;
+        const bool h = L->kind[f][0] == AXLB_HALO;
+        halo = halo || h;
         for (int d = 1; d < 3; ++d) {
-            if (is_wall(L->kind[f][d]) != w || (L->kind[f][d] == AXLB_PERIODIC) != p)
+            if (is_wall(L->kind[f][d]) != w || (L->kind[f][d] == AXLB_PERIODIC) != p ||
+                (L->kind[f][d] == AXLB_HALO) != h)
                 return fail(L, AXLB_EINVAL,
-                            "a face must be a wall, periodic or the axis for all three fields");
+                            "a face must be a wall, periodic, a halo or the axis for all three fields");
         }
     }
+    if (halo && (L->layout != AXLB_LAYOUT_AB || L->deriv != AXLB_DERIV_LAGGED))
+        return fail(L, AXLB_EINVAL, "HALO faces need the two-buffer, one-step layout");
     return AXLB_OK;
 }
 
@@ -347,6 +360,11 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     L->snap = (double *)p;
     p += L->lay.snap_bytes;
     L->red = (double *)p;
+    p += L->lay.red_bytes;
+    for (int f = 0; f < 2; ++f) {
+        L->halo[f] = p;
+        p += L->lay.halo_pop_bytes + L->lay.halo_lag_bytes;
+    }
     if (O.stream) {
         L->stream = (hipStream_t)O.stream;
         L->own_stream = false;
@@ -368,14 +386,14 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
 int axlb_set_bc(axlb_lattice *L, int face, int field, int kind, double value) {
     if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
     if (L->started) return fail(L, AXLB_ESTATE, "boundary rules are fixed once stepping started");
-    if (face < 0 || face > 3 || field < 0 || field > 2 || kind < 0 || kind > 5)
+    if (face < 0 || face > 3 || field < 0 || field > 2 || kind < 0 || kind > 6)
         return fail(L, AXLB_EINVAL, "face, field or kind out of range");
     if (L->cylinder && face == AXLB_R_IN && kind != AXLB_MIRROR)
         return fail(L, AXLB_EINVAL, "the inner face of a cylinder is the axis");
     if (kind == AXLB_MIRROR && !(L->cylinder && face == AXLB_R_IN))
         return fail(L, AXLB_EINVAL, "MIRROR is only the axis of a cylinder");
-    if (kind == AXLB_PERIODIC && face != AXLB_Z_LO && face != AXLB_Z_HI)
-        return fail(L, AXLB_EINVAL, "PERIODIC is only for z faces");
+    if ((kind == AXLB_PERIODIC || kind == AXLB_HALO) && face != AXLB_Z_LO && face != AXLB_Z_HI)
+        return fail(L, AXLB_EINVAL, "PERIODIC and HALO are only for z faces");
     if (field == AXLB_FLOW && (kind == AXLB_DIRICHLET || kind == AXLB_OMEGA_R || kind == AXLB_ADIABATIC))
         return fail(L, AXLB_EINVAL, "FLOW walls are NOSLIP");
     if (field == AXLB_THERMAL && (kind == AXLB_NOSLIP || kind == AXLB_OMEGA_R))
@@ -728,6 +746,48 @@ int axlb_autotune(axlb_lattice *L, int steps_per_trial, double *ms_per_step, int
     if (best_tile != L->tile || L->tile != tile0) drop_graphs(L);
     L->tile = best_tile;
     if (best) *best = best_tile;
+    return AXLB_OK;
+}
+
+int axlb_halo_bytes(const axlb_lattice *L, size_t *bytes) {
+    if (!L || !bytes) return fail(nullptr, AXLB_EINVAL, "NULL argument");
+    *bytes = L->lay.halo_pop_bytes + L->lay.halo_lag_bytes;
+    return AXLB_OK;
+}
+
+int axlb_halo_export(axlb_lattice *L, int face, void *device_dst) {
+    if (!L || !device_dst) return fail(L, AXLB_EINVAL, "NULL argument");
+    if (face != AXLB_Z_LO && face != AXLB_Z_HI) return fail(L, AXLB_EINVAL, "halo faces are z faces");
+    if (L->layout != AXLB_LAYOUT_AB) return fail(L, AXLB_EINVAL, "halos need the AB layout");
+    int rc = set_device(L);
+    if (rc) return rc;
+    // the row next to the face, of the state the next step reads
+    const long long row = face == AXLB_Z_LO ? 0 : L->Nz - 1;
+    const size_t es = storage_size(L->storage);
+    const size_t pitch = (size_t)L->lay.pitch, plane = (size_t)L->lay.plane;
+    char *dst = (char *)device_dst;
+    const char *pop = (const char *)L->pop[L->cur] + row * pitch * es;
+    HIP_TRY(L, hipMemcpy2DAsync(dst, pitch * es, pop, plane * es, L->Nr * es, NPOP,
+                                hipMemcpyDeviceToDevice, L->stream));
+    const char *lag = (const char *)L->lag[L->cur];
+    char *hl = dst + L->lay.halo_pop_bytes;
+    HIP_TRY(L, hipMemcpy2DAsync(hl, pitch * sizeof(LagT), lag + row * pitch * sizeof(LagT),
+                                plane * sizeof(LagT), L->Nr * sizeof(LagT), 3,
+                                hipMemcpyDeviceToDevice, L->stream));
+    HIP_TRY(L, hipMemcpyAsync(hl + 3 * pitch * sizeof(LagT),
+                              lag + 3 * plane * sizeof(LagT) + row * pitch * sizeof(float),
+                              L->Nr * sizeof(float), hipMemcpyDeviceToDevice, L->stream));
+    return AXLB_OK;
+}
+
+int axlb_halo_import(axlb_lattice *L, int face, const void *device_src) {
+    if (!L || !device_src) return fail(L, AXLB_EINVAL, "NULL argument");
+    if (face != AXLB_Z_LO && face != AXLB_Z_HI) return fail(L, AXLB_EINVAL, "halo faces are z faces");
+    int rc = set_device(L);
+    if (rc) return rc;
+    HIP_TRY(L, hipMemcpyAsync(L->halo[face - AXLB_Z_LO], device_src,
+                              L->lay.halo_pop_bytes + L->lay.halo_lag_bytes,
+                              hipMemcpyDeviceToDevice, L->stream));
     return AXLB_OK;
 }
 

@@ -11,7 +11,7 @@ namespace axlb {
 // Faces, distributions and boundary kinds (numbering of include/axlb.h).
 enum { R_IN = 0, R_OUT = 1, Z_LO = 2, Z_HI = 3 };
 enum { FLOW = 0, SWIRL = 1, THERMAL = 2 };
-enum { NOSLIP = 0, PERIODIC = 1, MIRROR = 2, DIRICHLET = 3, OMEGA_R = 4, ADIABATIC = 5 };
+enum { NOSLIP = 0, PERIODIC = 1, MIRROR = 2, DIRICHLET = 3, OMEGA_R = 4, ADIABATIC = 5, HALO = 6 };
 
 // Plane numbering of the population buffer: f_0..f_8, g_0..g_4, h_0..h_4.
 constexpr int NPOP = 19;
@@ -66,6 +66,12 @@ struct KParams {
     unsigned long long kinds;         // boundary kind of (face, field) in bits
                                       // 4 (3 face + field) .. +3
     float val[4][3];                  // imposed u_theta / T, or Omega
+    // HALO z faces (index 0: Z_LO, 1: Z_HI): the neighbouring row of the
+    // adjacent slab, populations as 19 planes of `pitch` elements of the
+    // storage type, then its lagged fields as a block of `pitch`-element
+    // planes (lag_ld layout)
+    const void *halo_pop[2];
+    const LagT *halo_lag[2];
 };
 
 __host__ __device__ __forceinline__ int kind_of(const KParams &P, int face, int fld) {

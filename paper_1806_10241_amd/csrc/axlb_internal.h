@@ -16,7 +16,9 @@ constexpr int RED_BLOCKS = 256;   // partial sums of the FP64 reductions
 struct Layout {
     int pitch;                 // row pitch in elements (multiple of 64)
     long long plane;           // elements per plane
-    size_t pop_bytes, lag_bytes, fld_bytes, snap_bytes, red_bytes, total;
+    size_t pop_bytes, lag_bytes, fld_bytes, snap_bytes, red_bytes;
+    size_t halo_pop_bytes, halo_lag_bytes;  // one z face's halo row: populations, lagged fields
+    size_t total;
 };
 
 size_t storage_size(int storage);
@@ -41,6 +43,7 @@ struct axlb_lattice {
     void *pop[2] = {nullptr, nullptr};
     axlb::LagT *lag[2] = {nullptr, nullptr};
     double *fld = nullptr, *snap = nullptr, *red = nullptr;
+    char *halo[2] = {nullptr, nullptr};  // halo rows of the z faces (HALO kind)
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     bool use_graphs = true;
     int tile = 0;  // step-kernel tile shape (see tile_shape)

@@ -66,15 +66,20 @@ __device__ __forceinline__ float wall_value(const KParams &P, int face, float ym
 // ----------------------------------------------------------------------------
 // Population sources for the pulls: src(p, i, j) is the value in plane p
 // (0..18) at node (i, j), where i may lie one row beyond a periodic z face
-// (the source then supplies the periodic image).  GlobalPops reads a
-// population buffer in device memory.
+// (the source then supplies the periodic image) or a HALO face.
+// GlobalPops reads a population buffer in device memory.
+// A row beyond a HALO z face comes from that face's halo row instead.
 template <class S>
 struct GlobalPops {
     const KParams &P;
     const S *A;
     __device__ __forceinline__ float operator()(int p, int i, int j) const {
-        if (i < 0) i += P.Nz;
-        else if (i >= P.Nz) i -= P.Nz;
+        if ((unsigned)i >= (unsigned)P.Nz) {
+            const int f = i < 0 ? 0 : 1;
+            if (kind_of(P, Z_LO + f, FLOW) == HALO)
+                return Conv<S>::ld(static_cast<const S *>(P.halo_pop[f]) + p * P.pitch + j);
+            i += i < 0 ? P.Nz : -P.Nz;
+        }
         return Conv<S>::ld(A + p * P.plane + (long long)i * P.pitch + j);
     }
 };
@@ -219,7 +224,7 @@ __device__ __forceinline__ float field_at(const KParams &P, const Get &get, int 
     const int face = nj < 0 ? R_IN : (nj >= P.Nr ? R_OUT : (ni < 0 ? Z_LO : Z_HI));
     const int fld = v <= 1 ? FLOW : (v == 2 ? SWIRL : THERMAL);
     const int k = kind_of(P, face, fld);
-    if (k == PERIODIC) return get(v, di, dj);
+    if (k == PERIODIC || k == HALO) return get(v, di, dj);
     const float q1 = get(v, 0, 0);
     if (k == MIRROR) return (v == 0 || v == 3) ? q1 : -q1;
     if (k == ADIABATIC) return q1;
@@ -253,15 +258,19 @@ struct TileSource {
 };
 
 // The lagged fields of the previous step as a field source (periodic
-// images wrap along z).
+// images wrap along z; beyond a HALO face, the halo row's fields).
 struct LagSource {
     const KParams &P;
     const LagT *M;
     int i, j;
     __device__ __forceinline__ float operator()(int v, int di, int dj) const {
         int ni = i + di;
-        if (ni < 0) ni += P.Nz;
-        else if (ni >= P.Nz) ni -= P.Nz;
+        if ((unsigned)ni >= (unsigned)P.Nz) {
+            const int f = ni < 0 ? 0 : 1;
+            if (kind_of(P, Z_LO + f, FLOW) == HALO)
+                return lag_ld(P.halo_lag[f], v, (long long)P.pitch, j + dj);
+            ni += ni < 0 ? P.Nz : -P.Nz;
+        }
         return lag_ld(M, v, P.plane, (long long)ni * P.pitch + (j + dj));
     }
 };

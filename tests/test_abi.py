@@ -33,7 +33,8 @@ def test_state_bytes_and_argument_checks():
     n16 = axlb.state_bytes(1024, 2048, "f16", "aa")
     nab = axlb.state_bytes(1024, 2048, "f32", "ab")
     pop32 = 19 * 1024 * 2048 * 4
-    assert n32 - n16 == pop32 // 2
+    halo32 = 2 * 19 * 1024 * 4  # the halo rows of the two z faces
+    assert n32 - n16 == (pop32 + halo32) // 2
     assert nab - n32 == pop32
     with pytest.raises(axlb.AxlbError):
         axlb.state_bytes(1, 10)

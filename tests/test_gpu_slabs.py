@@ -1,0 +1,102 @@
+"""A lattice cut along z into slabs, as one GPU's share of a multi-GPU run
+would be: each slab is a lattice of its own whose cut faces are HALO faces,
+and before every step each slab's boundary rows are packed
+(axlb_halo_export), moved (here a device copy, between GPUs a send and a
+receive) and unpacked into the neighbours' halos (axlb_halo_import).  The
+slabs must reproduce the uncut lattice bit for bit (FP32, two buffers)."""
+import copy
+
+import numpy as np
+import pytest
+
+from conftest import say
+from test_gpu_parity import FIELDS, smooth_fields
+from paper_1806_10241_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def slab_cases(case, init, rows):
+    """Cases of the slabs of `case` with `rows` rows each, and their fields."""
+    periodic = case["bc"][(I.Z_LO, I.FLOW)][0] == I.PERIODIC
+    out, i0 = [], 0
+    for k, n in enumerate(rows):
+        c = copy.deepcopy({key: v for key, v in case.items() if key != "fields"})
+        c["Nz"] = n
+        for face, cut in ((I.Z_LO, k > 0 or periodic), (I.Z_HI, k < len(rows) - 1 or periodic)):
+            if cut:
+                for fld in (I.FLOW, I.SWIRL, I.THERMAL):
+                    c["bc"][(face, fld)] = (6, 0.0)
+        out.append((c, {name: a[i0:i0 + n] for name, a in init.items()}))
+        i0 += n
+    return out
+
+
+def exchange(torch, slabs, bufs, periodic):
+    from paper_1806_10241_amd import axlb
+    n = len(slabs)
+    for s, lat in enumerate(slabs):
+        lat.halo_export(I.Z_LO, bufs[s][0].data_ptr())
+        lat.halo_export(I.Z_HI, bufs[s][1].data_ptr())
+    for lat in slabs:
+        lat.sync()
+    for s, lat in enumerate(slabs):
+        if s > 0 or periodic:
+            lat.halo_import(I.Z_LO, bufs[(s - 1) % n][1].data_ptr())  # the row below, its top row
+        if s < n - 1 or periodic:
+            lat.halo_import(I.Z_HI, bufs[(s + 1) % n][0].data_ptr())  # the row above, its bottom row
+    for lat in slabs:
+        lat.sync()
+
+
+@pytest.mark.parametrize("name", ["lid", "annulus", "periodic"])
+def test_slabs_reproduce_the_uncut_lattice(gpu, name):
+    say("slabs", name)
+    from paper_1806_10241_amd import axlb
+    torch = gpu
+    if name == "lid":
+        case, rows = I.rotating_lid_cylinder(Nr=130, Nz=200, Re=300.0, Ri=0.5), [50, 70, 31, 49]
+    elif name == "annulus":
+        case, rows = I.annulus_convection(Nr=96, Nz=150, Ra=1e5, seed=21), [64, 1, 85]
+    else:
+        case, rows = I.couette_poiseuille_conduction(Nr=70, Nz=18, r_inner=20.0, u_wall=0.02,
+                                                     g=2e-5), [6, 5, 7]
+    init = smooth_fields(case["Nz"], case["Nr"], 3)
+    full = axlb.Lattice(case, layout="ab", init_fields=False)
+    full.set_fields(**init)
+    periodic = case["bc"][(I.Z_LO, I.FLOW)][0] == I.PERIODIC
+    slabs = []
+    for c, f in slab_cases(case, init, rows):
+        lat = axlb.Lattice(c, layout="ab", init_fields=False)
+        lat.set_fields(**f)
+        slabs.append(lat)
+    nb = slabs[0].halo_bytes()
+    bufs = [(torch.empty(nb, dtype=torch.uint8, device="cuda"),
+             torch.empty(nb, dtype=torch.uint8, device="cuda")) for _ in slabs]
+    for _ in range(120):
+        exchange(torch, slabs, bufs, periodic)
+        for lat in slabs:
+            lat.step(1)
+    exchange(torch, slabs, bufs, periodic)  # the reported fields read the halos too
+    full.step(120)
+    F = full.fields()
+    i0 = 0
+    for lat, n in zip(slabs, rows):
+        G = lat.fields()
+        for k in FIELDS:
+            assert np.array_equal(G[k], F[k][i0:i0 + n]), (name, i0, k)
+        i0 += n
+
+
+def test_halo_faces_are_checked(gpu):
+    from paper_1806_10241_amd import axlb
+    c = I.couette_poiseuille_conduction(Nr=30, Nz=8)
+    for fld in (I.FLOW, I.SWIRL, I.THERMAL):
+        c["bc"][(I.Z_LO, fld)] = (6, 0.0)
+        c["bc"][(I.Z_HI, fld)] = (6, 0.0)
+    lat = axlb.Lattice(c)  # the single-buffer layout cannot take halos
+    with pytest.raises(axlb.AxlbError):
+        lat.step(1)
+    lat = axlb.Lattice(c, layout="ab")
+    with pytest.raises(axlb.AxlbError):
+        lat.halo_export(I.R_IN, 0)
