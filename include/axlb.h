@@ -137,7 +137,8 @@ int axlb_state_bytes(int Nr, int Nz, int storage, int layout, size_t *bytes);
 
 /* Creates a lattice at rest (rho = 1, u = 0, T = T_ref).
  *  Nr, Nz  fluid nodes along r and z (Nr >= 2, Nz >= 1; Nz >= 2 unless z is
- *          periodic).
+ *          periodic; Nz times Nr rounded up to a multiple of 64 at most 2^30,
+ *          about 10^9 nodes).
  *  nu      kinematic viscosity; omega_4,5 = omega^psi_1,2 = 1/(3 nu + 1/2)
  *          (text after eq. 17 and eq. 34); nu > 0 (tau > 1/2).
  *  alpha   thermal diffusivity; omega^phi_1,2 = 1/(3 alpha + 1/2) (after

@@ -262,8 +262,10 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     if (!out) return fail(nullptr, AXLB_EINVAL, "out is NULL");
     *out = nullptr;
     if (!geo) return fail(nullptr, AXLB_EINVAL, "geometry is NULL");
-    if (Nr < 2 || Nz < 1 || (long long)Nr * Nz > (1LL << 31))
-        return fail(nullptr, AXLB_EINVAL, "Nr >= 2, Nz >= 1 and Nr*Nz < 2^31 required");
+    // the step kernel addresses a plane with 32-bit byte offsets (4 bytes per node)
+    if (Nr < 2 || Nz < 1 || (long long)Nz * (((long long)Nr + 63) / 64 * 64) > (1LL << 30))
+        return fail(nullptr, AXLB_EINVAL,
+                    "Nr >= 2, Nz >= 1 and Nz * (Nr rounded up to 64) <= 2^30 required");
     if (geo->kind != AXLB_ANNULUS && geo->kind != AXLB_CYLINDER)
         return fail(nullptr, AXLB_EINVAL, "unknown geometry kind");
     if (geo->kind == AXLB_ANNULUS && !(geo->r_inner > 0.0 && std::isfinite(geo->r_inner)))

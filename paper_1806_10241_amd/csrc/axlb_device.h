@@ -74,6 +74,24 @@ struct KParams {
     const LagT *halo_lag[2];
 };
 
+// Plane addresses of one step launch, for the tile workgroups of the step
+// kernel: population p (f 0..8, g 9..13, h 14..18) of node n is read at
+// rd[p] + n * sizeof(S) and written at wr[p] + n * sizeof(S), the streaming
+// shift and slot exchange of the launch's phase being folded into the
+// addresses on the host; lagged field v of node n is read at lrd[v] and
+// written at lwr[v] + n * (element size), and uy_up / uy_dn address the
+// u_y plane one row above / below.  The per-node offset is a 32-bit byte
+// offset added to a uniform base, which gfx950 takes directly (an SGPR
+// base plus a VGPR offset) instead of a 64-bit address per access; planes
+// therefore hold at most 2^30 nodes.
+struct Planes {
+    const char *rd[NPOP];
+    char *wr[NPOP];
+    const char *lrd[NLAG];
+    char *lwr[NLAG];
+    const char *uy_up, *uy_dn;
+};
+
 __host__ __device__ __forceinline__ int kind_of(const KParams &P, int face, int fld) {
     return (int)((P.kinds >> (4 * (3 * face + fld))) & 15ull);
 }

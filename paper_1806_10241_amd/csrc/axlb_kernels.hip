@@ -31,7 +31,8 @@ namespace axlb {
 // nodes; the AA even phase streams within each node's own slots, so its
 // tiles take every node.  Tile workgroups are XCD-remapped as in tile_of.
 template <class S, int MODE, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const S *src, S *dst,
+__global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const Planes A,
+                                                   const S *src, S *dst,
                                                    const LagT *__restrict__ Mprev,
                                                    LagT *__restrict__ Mnext) {
     constexpr bool SPLIT = MODE != MODE_AA_EVEN;
@@ -53,10 +54,10 @@ __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const S *src,
     const int i = (u / gx) * BY + (int)threadIdx.x / BX;
     if (SPLIT) {
         if (!interior_node(P, i, j)) return;  // edge nodes and the ragged tail
-        update_node<S, MODE>(P, src, dst, Mprev, Mnext, i, j, true);
+        update_planes<S>(P, A, i, j, true);
     } else {
         if (i >= P.Nz || j >= P.Nr) return;
-        update_node<S, MODE>(P, src, dst, Mprev, Mnext, i, j, interior_node(P, i, j));
+        update_planes<S>(P, A, i, j, interior_node(P, i, j));
     }
 }
 
@@ -248,15 +249,68 @@ static dim3 grid_for(const KParams &P, int bx, int by) {
 
 static dim3 step_grid(const KParams &P) { return grid_for(P, TX, TY); }
 
+// Population p = OFF + q of distribution FLD: where node n reads it and
+// where it writes it in the given phase (element offsets from the buffer
+// start, before the node offset n is added).
+template <int FLD>
+static void plane_offsets(const KParams &P, int mode, int q, long long &rd, long long &wr) {
+    using L = Lat<FLD>;
+    const long long dn = (long long)L::ex(q) * P.pitch + L::ey(q);
+    if (mode == MODE_AA_EVEN) {
+        rd = (L::OFF + q) * P.plane;
+        wr = (L::OFF + L::opp(q)) * P.plane;
+    } else if (mode == MODE_AA_ODD) {
+        rd = (L::OFF + L::opp(q)) * P.plane - dn;
+        wr = (L::OFF + q) * P.plane + dn;
+    } else {
+        rd = (L::OFF + q) * P.plane - dn;
+        wr = (L::OFF + q) * P.plane;
+    }
+}
+
+// The plane addresses of one launch (see Planes).  Computed as integers:
+// a read address of the odd phase or the pull may lie before its plane
+// (the node offset brings it back inside for every node that uses it).
+template <class S>
+static Planes planes_for(const KParams &P, int mode, const S *src, S *dst, const LagT *Mprev,
+                         LagT *Mnext) {
+    Planes A{};
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    const long long es = (long long)sizeof(S);
+    auto set = [&](int p, long long rd, long long wr) {
+        A.rd[p] = (const char *)(a + (uintptr_t)(rd * es));
+        A.wr[p] = (char *)(b + (uintptr_t)(wr * es));
+    };
+    long long rd, wr;
+    for (int q = 0; q < 9; ++q) {
+        plane_offsets<FLOW>(P, mode, q, rd, wr);
+        set(q, rd, wr);
+    }
+    for (int q = 0; q < 5; ++q) {
+        plane_offsets<SWIRL>(P, mode, q, rd, wr);
+        set(GOFF + q, rd, wr);
+        plane_offsets<THERMAL>(P, mode, q, rd, wr);
+        set(HOFF + q, rd, wr);
+    }
+    for (int v = 0; v < NLAG; ++v) {
+        A.lrd[v] = (const char *)(Mprev + v * P.plane);
+        A.lwr[v] = (char *)(Mnext + v * P.plane);
+    }
+    A.uy_up = (const char *)((uintptr_t)A.lrd[1] + (uintptr_t)(2 * P.pitch));
+    A.uy_dn = (const char *)((uintptr_t)A.lrd[1] - (uintptr_t)(2 * P.pitch));
+    return A;
+}
+
 template <class S, int BX, int BY>
 static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT *Mprev,
                              LagT *Mnext, hipStream_t st) {
     const int edges = mode == MODE_AA_EVEN ? 0 : edge_blocks(P.Nr, P.Nz, BX * BY);
     const dim3 grid(grid_for(P, BX, BY).x + edges), block(BX * BY);
+    const Planes A = planes_for<S>(P, mode, a, mode == MODE_AB ? b : a, Mprev, Mnext);
     switch (mode) {
-    case MODE_AB: k_step<S, MODE_AB, BX, BY><<<grid, block, 0, st>>>(P, a, b, Mprev, Mnext); break;
-    case MODE_AA_ODD: k_step<S, MODE_AA_ODD, BX, BY><<<grid, block, 0, st>>>(P, a, a, Mprev, Mnext); break;
-    default: k_step<S, MODE_AA_EVEN, BX, BY><<<grid, block, 0, st>>>(P, a, a, Mprev, Mnext); break;
+    case MODE_AB: k_step<S, MODE_AB, BX, BY><<<grid, block, 0, st>>>(P, A, a, b, Mprev, Mnext); break;
+    case MODE_AA_ODD: k_step<S, MODE_AA_ODD, BX, BY><<<grid, block, 0, st>>>(P, A, a, a, Mprev, Mnext); break;
+    default: k_step<S, MODE_AA_EVEN, BX, BY><<<grid, block, 0, st>>>(P, A, a, a, Mprev, Mnext); break;
     }
 }
 

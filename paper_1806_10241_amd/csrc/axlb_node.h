@@ -657,4 +657,62 @@ __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *d
     lag_st(Mnext, 3, P.plane, n, H.dphi);
 }
 
+// ----------------------------------------------------------------------------
+// The same update through a launch's plane addresses (Planes), for the tile
+// workgroups of the step kernel: valid for every node in the AA even phase
+// (each node reads and writes its own slots) and for interior nodes in the
+// AA odd phase and the two-buffer pull.  The arithmetic, the rounding keys
+// and the derivative stencils are update_node's, so both give identical
+// bits; only the address arithmetic differs (one 32-bit offset per node).
+template <class S>
+__device__ __forceinline__ float ld_plane(const char *base, unsigned off) {
+    return Conv<S>::ld(reinterpret_cast<const S *>(base + off));
+}
+__device__ __forceinline__ float lag_plane(const char *base, unsigned off) {
+    return lag_h(reinterpret_cast<const LagT *>(base + off));
+}
+
+template <class S>
+__device__ __forceinline__ void update_planes(const KParams &P, const Planes &A, int i, int j,
+                                              bool interior) {
+    const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+    const unsigned o = n * (unsigned)sizeof(S), o2 = n * 2u, o4 = n * 4u;
+    float f[9], g[5], h[5];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) f[q] = ld_plane<S>(A.rd[q], o);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        g[q] = ld_plane<S>(A.rd[GOFF + q], o);
+        h[q] = ld_plane<S>(A.rd[HOFF + q], o);
+    }
+    float d[5];
+    if (interior) {
+        d[0] = 0.5f * (lag_plane(A.uy_up, o2) - lag_plane(A.uy_dn, o2));
+        d[1] = 0.5f * (lag_plane(A.lrd[0], o2 + 2u) - lag_plane(A.lrd[0], o2 - 2u));
+        d[2] = 0.5f * (lag_plane(A.lrd[1], o2 + 2u) - lag_plane(A.lrd[1], o2 - 2u));
+        d[3] = 0.5f * (lag_plane(A.lrd[2], o2 + 2u) - lag_plane(A.lrd[2], o2 - 2u));
+        d[4] = 0.5f * (*reinterpret_cast<const float *>(A.lrd[3] + (o4 + 4u)) -
+                       *reinterpret_cast<const float *>(A.lrd[3] + (o4 - 4u)));
+    } else {
+        differences(P, LagSource{P, reinterpret_cast<const LagT *>(A.lrd[0]), i, j}, i, j, d);
+    }
+    const Half H = relax_node(P, j, f, g, h, d);
+    // Register copies of the offsets, made after the branch above: the
+    // compiler chooses the SGPR-base address form per basic block, only for
+    // an offset it sees widened from 32 bits in the same block.
+    unsigned so = o, so2 = o2, so4 = o4;
+    asm volatile("" : "+v"(so), "+v"(so2), "+v"(so4));
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Conv<S>::st(reinterpret_cast<S *>(A.wr[q] + so), f[q], skey(i, j, q));
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        Conv<S>::st(reinterpret_cast<S *>(A.wr[GOFF + q] + so), g[q], skey(i, j, GOFF + q));
+        Conv<S>::st(reinterpret_cast<S *>(A.wr[HOFF + q] + so), h[q], skey(i, j, HOFF + q));
+    }
+    *reinterpret_cast<LagT *>(A.lwr[0] + so2) = __float2half_rn(H.ux * LAG_SCALE);
+    *reinterpret_cast<LagT *>(A.lwr[1] + so2) = __float2half_rn(H.uy * LAG_SCALE);
+    *reinterpret_cast<LagT *>(A.lwr[2] + so2) = __float2half_rn(H.psi * H.irho * LAG_SCALE);
+    *reinterpret_cast<float *>(A.lwr[3] + so4) = H.dphi;
+}
+
 }  // namespace axlb
