@@ -88,7 +88,7 @@ def bench_batched(n, steps, warmup, baseline_steps):
     lats = [axlb.Lattice(c) for c in cases]
     nodes = sum(c["Nr"] * c["Nz"] for c in cases)
     b = axlb.Batch(lats)
-    tile, blocks, _ = b.autotune(steps_per_trial=8)
+    tile, blocks, _ = b.autotune(steps_per_trial=20)
     b.step(warmup)
     b.sync()
     t0 = time.perf_counter()

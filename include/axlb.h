@@ -268,8 +268,9 @@ int axlb_batch_set_schedule(axlb_batch *b, int tile, int blocks);
 int axlb_batch_get_schedule(const axlb_batch *b, int *tile, int *blocks);
 /* Times every tile shape with each of the AXLB_NSCHEDULES schedules (one
  * workgroup per entry, 4, 8 and 16 persistent workgroups per compute unit)
- * for steps_per_trial steps, restores the members' state, keeps the
- * fastest.  ms_per_step[AXLB_NTILES * AXLB_NSCHEDULES] may be NULL. */
+ * for steps_per_trial steps (group by group, as the bundles of
+ * axlb_batch_step run), restores the members' state, keeps the fastest.
+ * ms_per_step[AXLB_NTILES * AXLB_NSCHEDULES] may be NULL. */
 int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
                         int *best_tile, int *best_blocks);
 void axlb_batch_destroy(axlb_batch *b);

@@ -36,6 +36,7 @@ struct InstDesc {
     int tile_begin;  // first work-list entry of this member
     int gx;          // tiles along r
     int nedge;       // edge chunks, the member's first work-list entries
+    Planes pl[2];    // plane addresses of the even (0) and odd (1) AA phase
 };
 
 // Work-list entries are dealt to the 8 XCDs in 8 contiguous chunks, so that
@@ -69,11 +70,10 @@ __global__ void __launch_bounds__(BX *BY)
         const int i = (u / d->gx) * BY + (int)threadIdx.x / BX;
         if (odd) {
             if (!interior_node(d->P, i, j)) continue;
-            update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j, true);
+            update_planes<S>(d->P, d->pl[1], i, j, true);
         } else {
             if (i >= d->P.Nz || j >= d->P.Nr) continue;
-            update_node<S, MODE_AA_EVEN>(d->P, A, A, d->lag[1], d->lag[0], i, j,
-                                         interior_node(d->P, i, j));
+            update_planes<S>(d->P, d->pl[0], i, j, interior_node(d->P, i, j));
         }
     }
 }
@@ -168,6 +168,8 @@ static int build_worklist(axlb_batch *b) {
         d.pop = L->pop[0];
         d.lag[0] = L->lag[0];
         d.lag[1] = L->lag[1];
+        d.pl[0] = step_planes(L->P, L->storage, MODE_AA_EVEN, d.pop, d.pop, d.lag[1], d.lag[0]);
+        d.pl[1] = step_planes(L->P, L->storage, MODE_AA_ODD, d.pop, d.pop, d.lag[0], d.lag[1]);
         d.parity0 = (int)((L->steps - b->steps) & 1);
         d.gx = (L->Nr + bx - 1) / bx;
         const int gy = (L->Nz + by - 1) / by;
@@ -379,9 +381,12 @@ int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
         for (int sidx = 0; sidx < AXLB_NSCHEDULES && rc == AXLB_OK; ++sidx) {
             b->blocks = sched[sidx];
             for (int s = 0; s < 2 && rc == AXLB_OK; ++s, ++b->steps) rc = batch_launch(b, b->steps);
+            // the trial steps group by group, as a bundle does
             (void)hipEventRecord(e0, b->stream);
-            for (int s = 0; s < steps_per_trial && rc == AXLB_OK; ++s, ++b->steps)
-                rc = batch_launch(b, b->steps);
+            for (size_t g = 0; g + 1 < b->group.size() && rc == AXLB_OK; ++g)
+                for (int s = 0; s < steps_per_trial && rc == AXLB_OK; ++s)
+                    rc = batch_launch(b, b->steps + s, b->group[g], b->group[g + 1]);
+            b->steps += steps_per_trial;
             (void)hipEventRecord(e1, b->stream);
             float ms = 0.f;
             if (rc == AXLB_OK && (hipEventSynchronize(e1) != hipSuccess ||

@@ -271,12 +271,11 @@ static void plane_offsets(const KParams &P, int mode, int q, long long &rd, long
 // The plane addresses of one launch (see Planes).  Computed as integers:
 // a read address of the odd phase or the pull may lie before its plane
 // (the node offset brings it back inside for every node that uses it).
-template <class S>
-static Planes planes_for(const KParams &P, int mode, const S *src, S *dst, const LagT *Mprev,
-                         LagT *Mnext) {
+Planes step_planes(const KParams &P, int storage, int mode, const void *src, void *dst,
+                   const LagT *Mprev, LagT *Mnext) {
     Planes A{};
     const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
-    const long long es = (long long)sizeof(S);
+    const long long es = storage == STORE_F32 ? 4 : 2;
     auto set = [&](int p, long long rd, long long wr) {
         A.rd[p] = (const char *)(a + (uintptr_t)(rd * es));
         A.wr[p] = (char *)(b + (uintptr_t)(wr * es));
@@ -306,7 +305,8 @@ static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT 
                              LagT *Mnext, hipStream_t st) {
     const int edges = mode == MODE_AA_EVEN ? 0 : edge_blocks(P.Nr, P.Nz, BX * BY);
     const dim3 grid(grid_for(P, BX, BY).x + edges), block(BX * BY);
-    const Planes A = planes_for<S>(P, mode, a, mode == MODE_AB ? b : a, Mprev, Mnext);
+    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, mode, a,
+                                 mode == MODE_AB ? b : a, Mprev, Mnext);
     switch (mode) {
     case MODE_AB: k_step<S, MODE_AB, BX, BY><<<grid, block, 0, st>>>(P, A, a, b, Mprev, Mnext); break;
     case MODE_AA_ODD: k_step<S, MODE_AA_ODD, BX, BY><<<grid, block, 0, st>>>(P, A, a, a, Mprev, Mnext); break;

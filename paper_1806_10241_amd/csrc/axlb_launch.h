@@ -20,6 +20,11 @@ void tile_shape(int tile, int *bx, int *by);
 // mode: 0 = AB pull (src -> dst), 1 = AA odd phase, 2 = AA even phase (src == dst).
 hipError_t launch_step(const KParams &P, int storage, int tile, int mode, void *src, void *dst,
                        const LagT *Mprev, LagT *Mnext, hipStream_t st);
+// The plane addresses (Planes) of one step of the given mode: populations
+// read from src and written to dst (src == dst in the AA phases), lagged
+// fields read from Mprev and written to Mnext.
+Planes step_planes(const KParams &P, int storage, int mode, const void *src, void *dst,
+                   const LagT *Mprev, LagT *Mnext);
 hipError_t launch_fields(const KParams &P, int storage, int mode, const void *src,
                          const LagT *Mprev, double *out, hipStream_t st);
 // Current-step derivatives (two buffers, pull): one step src -> dst, or the

@@ -3,6 +3,8 @@
 // kernels so that both perform identical arithmetic.  Internal.
 #pragma once
 
+#include <type_traits>
+
 #include "axlb_device.h"
 
 namespace axlb {
@@ -658,20 +660,44 @@ __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *d
 }
 
 // ----------------------------------------------------------------------------
+// Accesses through device-memory (address space 1) pointers: the compiler
+// then emits global instructions with an SGPR base and a 32-bit VGPR
+// offset, also where the base was read from memory (a plain pointer read
+// from memory would give flat instructions with a 64-bit address each).
+using gbyte = __attribute__((address_space(1))) char;
+template <class T>
+__device__ __forceinline__ T gload(const char *base, unsigned off) {
+    return *(const __attribute__((address_space(1))) T *)((const gbyte *)base + off);
+}
+template <class T>
+__device__ __forceinline__ void gstore(char *base, unsigned off, T v) {
+    *(__attribute__((address_space(1))) T *)((gbyte *)base + off) = v;
+}
+template <class S>
+using StoreBits = std::conditional_t<sizeof(S) == 4, float, unsigned short>;
+
+template <class S>
+__device__ __forceinline__ float ld_plane(const char *base, unsigned off) {
+    const S v = __builtin_bit_cast(S, gload<StoreBits<S>>(base, off));
+    return Conv<S>::ld(&v);
+}
+template <class S>
+__device__ __forceinline__ void st_plane(char *base, unsigned off, float x, unsigned key) {
+    S v;
+    Conv<S>::st(&v, x, key);
+    gstore(base, off, __builtin_bit_cast(StoreBits<S>, v));
+}
+__device__ __forceinline__ float lag_plane(const char *base, unsigned off) {
+    const LagT v = __builtin_bit_cast(LagT, gload<unsigned short>(base, off));
+    return lag_h(&v);
+}
+
 // The same update through a launch's plane addresses (Planes), for the tile
 // workgroups of the step kernel: valid for every node in the AA even phase
 // (each node reads and writes its own slots) and for interior nodes in the
 // AA odd phase and the two-buffer pull.  The arithmetic, the rounding keys
 // and the derivative stencils are update_node's, so both give identical
 // bits; only the address arithmetic differs (one 32-bit offset per node).
-template <class S>
-__device__ __forceinline__ float ld_plane(const char *base, unsigned off) {
-    return Conv<S>::ld(reinterpret_cast<const S *>(base + off));
-}
-__device__ __forceinline__ float lag_plane(const char *base, unsigned off) {
-    return lag_h(reinterpret_cast<const LagT *>(base + off));
-}
-
 template <class S>
 __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A, int i, int j,
                                               bool interior) {
@@ -691,8 +717,7 @@ __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A,
         d[1] = 0.5f * (lag_plane(A.lrd[0], o2 + 2u) - lag_plane(A.lrd[0], o2 - 2u));
         d[2] = 0.5f * (lag_plane(A.lrd[1], o2 + 2u) - lag_plane(A.lrd[1], o2 - 2u));
         d[3] = 0.5f * (lag_plane(A.lrd[2], o2 + 2u) - lag_plane(A.lrd[2], o2 - 2u));
-        d[4] = 0.5f * (*reinterpret_cast<const float *>(A.lrd[3] + (o4 + 4u)) -
-                       *reinterpret_cast<const float *>(A.lrd[3] + (o4 - 4u)));
+        d[4] = 0.5f * (gload<float>(A.lrd[3], o4 + 4u) - gload<float>(A.lrd[3], o4 - 4u));
     } else {
         differences(P, LagSource{P, reinterpret_cast<const LagT *>(A.lrd[0]), i, j}, i, j, d);
     }
@@ -703,16 +728,17 @@ __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A,
     unsigned so = o, so2 = o2, so4 = o4;
     asm volatile("" : "+v"(so), "+v"(so2), "+v"(so4));
 #pragma unroll
-    for (int q = 0; q < 9; ++q) Conv<S>::st(reinterpret_cast<S *>(A.wr[q] + so), f[q], skey(i, j, q));
+    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], so, f[q], skey(i, j, q));
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        Conv<S>::st(reinterpret_cast<S *>(A.wr[GOFF + q] + so), g[q], skey(i, j, GOFF + q));
-        Conv<S>::st(reinterpret_cast<S *>(A.wr[HOFF + q] + so), h[q], skey(i, j, HOFF + q));
+        st_plane<S>(A.wr[GOFF + q], so, g[q], skey(i, j, GOFF + q));
+        st_plane<S>(A.wr[HOFF + q], so, h[q], skey(i, j, HOFF + q));
     }
-    *reinterpret_cast<LagT *>(A.lwr[0] + so2) = __float2half_rn(H.ux * LAG_SCALE);
-    *reinterpret_cast<LagT *>(A.lwr[1] + so2) = __float2half_rn(H.uy * LAG_SCALE);
-    *reinterpret_cast<LagT *>(A.lwr[2] + so2) = __float2half_rn(H.psi * H.irho * LAG_SCALE);
-    *reinterpret_cast<float *>(A.lwr[3] + so4) = H.dphi;
+    gstore(A.lwr[0], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.ux * LAG_SCALE)));
+    gstore(A.lwr[1], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.uy * LAG_SCALE)));
+    gstore(A.lwr[2], so2,
+           __builtin_bit_cast(unsigned short, __float2half_rn(H.psi * H.irho * LAG_SCALE)));
+    gstore(A.lwr[3], so4, H.dphi);
 }
 
 }  // namespace axlb
