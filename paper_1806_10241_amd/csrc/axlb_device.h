@@ -121,9 +121,15 @@ __device__ __forceinline__ unsigned mix32(unsigned x) {
 }
 
 template <class S> struct Conv;
+// Conv<S>::bits(v, key, r) gives the bit pattern st stores for v; the
+// 16-bit conversions write it into the low half of the register r and leave
+// its high half as it was, so a sequence of stores can reuse one register
+// instead of clearing a fresh one for each.
 template <> struct Conv<float> {
+    using Reg = int;
     __device__ static __forceinline__ float ld(const float *p) { return *p; }
     __device__ static __forceinline__ void st(float *p, float v, unsigned) { *p = v; }
+    __device__ static __forceinline__ float bits(float v, unsigned, Reg &) { return v; }
 };
 
 // 16-bit stores round stochastically with the gfx950 conversions
@@ -145,22 +151,32 @@ __device__ __forceinline__ unsigned sr_bits(float x, unsigned key) {
 // below the binary16 maximum for any population a stable run produces.
 constexpr float F16_SCALE = 256.f;
 template <> struct Conv<__half> {
+    using Reg = half2_t;
     __device__ static __forceinline__ float ld(const __half *p) {
         return __half2float(*p) * (1.f / F16_SCALE);
     }
-    __device__ static __forceinline__ void st(__half *p, float v, unsigned key) {
+    __device__ static __forceinline__ unsigned short bits(float v, unsigned key, Reg &r) {
         const float x = v * F16_SCALE;
-        const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(half2_t{0, 0}, x, sr_bits(x, key), false);
-        *p = __builtin_bit_cast(__half, h[0]);
+        r = __builtin_amdgcn_cvt_sr_f16_f32(r, x, sr_bits(x, key), false);
+        return __builtin_bit_cast(unsigned short, r[0]);
+    }
+    __device__ static __forceinline__ void st(__half *p, float v, unsigned key) {
+        Reg r{0, 0};
+        *p = __builtin_bit_cast(__half, bits(v, key, r));
     }
 };
 template <> struct Conv<__hip_bfloat16> {
+    using Reg = short2_t;
     __device__ static __forceinline__ float ld(const __hip_bfloat16 *p) {
         return __bfloat162float(*p);
     }
+    __device__ static __forceinline__ unsigned short bits(float v, unsigned key, Reg &r) {
+        r = __builtin_amdgcn_cvt_sr_bf16_f32(r, v, sr_bits(v, key), false);
+        return __builtin_bit_cast(unsigned short, r[0]);
+    }
     __device__ static __forceinline__ void st(__hip_bfloat16 *p, float v, unsigned key) {
-        const short2_t b = __builtin_amdgcn_cvt_sr_bf16_f32(short2_t{0, 0}, v, sr_bits(v, key), false);
-        *p = __builtin_bit_cast(__hip_bfloat16, b[0]);
+        Reg r{0, 0};
+        *p = __builtin_bit_cast(__hip_bfloat16, bits(v, key, r));
     }
 };
 

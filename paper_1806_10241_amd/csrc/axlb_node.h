@@ -369,15 +369,20 @@ __device__ __forceinline__ void collide_f(const KParams &P, float (&f)[9], const
               uy2 * ((1.f / 3.f) + kxx) + 4.f * ux * uy * kxy)) -
         2.f * p3 - 0.5f * uy2 * (3.f * p3 + p4) - 0.5f * ux2 * (3.f * p3 - p4) -
         4.f * ux * uy * p5 - 2.f * uy * p6 - 2.f * ux * p7;
+    // f += K p with the columns of K grouped so that shared partial sums
+    // are formed once
+    const float a = p0 - p3, ax = a + p4, ay = a - p4;
+    const float c = p0 + 2.f * p3 + p8, cu = p1 + p2, cv = p1 - p2;
+    const float s67 = p6 + p7, d67 = p7 - p6;
     f[0] += p0 - 4.f * (p3 - p8);
-    f[1] += p0 + p1 - p3 + p4 + 2.f * (p7 - p8);
-    f[2] += p0 + p2 - p3 - p4 + 2.f * (p6 - p8);
-    f[3] += p0 - p1 - p3 + p4 - 2.f * (p7 + p8);
-    f[4] += p0 - p2 - p3 - p4 - 2.f * (p6 + p8);
-    f[5] += p0 + p1 + p2 + 2.f * p3 + p5 - p6 - p7 + p8;
-    f[6] += p0 - p1 + p2 + 2.f * p3 - p5 - p6 + p7 + p8;
-    f[7] += p0 - p1 - p2 + 2.f * p3 + p5 + p6 + p7 + p8;
-    f[8] += p0 + p1 - p2 + 2.f * p3 - p5 + p6 - p7 + p8;
+    f[1] += (ax + p1) + 2.f * (p7 - p8);
+    f[3] += (ax - p1) - 2.f * (p7 + p8);
+    f[2] += (ay + p2) + 2.f * (p6 - p8);
+    f[4] += (ay - p2) - 2.f * (p6 + p8);
+    f[5] += (c + cu) + (p5 - s67);
+    f[7] += (c - cu) + (p5 + s67);
+    f[6] += (c - cv) + (d67 - p5);
+    f[8] += (c + cv) - (d67 + p5);
 }
 
 // Cascaded D2Q5 collision for an advected scalar s = s_ref + ds stored as
@@ -400,11 +405,12 @@ __device__ __forceinline__ void collide_adv(float (&g)[5], float ux, float uy, f
     const float q4 = 0.25f * o4 *
                          (-(kxx - kyy) + 2.f * (ux * kx - uy * ky) - (ux * ux - uy * uy) * s) +
                      ux * q1 - uy * q2;
+    const float a = q0 + q3, ax = a + q4, ay = a - q4;
     g[0] += q0 - 4.f * q3;
-    g[1] += q0 + q1 + q3 + q4;
-    g[2] += q0 + q2 + q3 - q4;
-    g[3] += q0 - q1 + q3 + q4;
-    g[4] += q0 - q2 + q3 - q4;
+    g[1] += ax + q1;
+    g[3] += ax - q1;
+    g[2] += ay + q2;
+    g[4] += ay - q2;
 }
 
 // Output moments (eq. 18, 35, 47) and central differences of the lagged
@@ -682,10 +688,9 @@ __device__ __forceinline__ float ld_plane(const char *base, unsigned off) {
     return Conv<S>::ld(&v);
 }
 template <class S>
-__device__ __forceinline__ void st_plane(char *base, unsigned off, float x, unsigned key) {
-    S v;
-    Conv<S>::st(&v, x, key);
-    gstore(base, off, __builtin_bit_cast(StoreBits<S>, v));
+__device__ __forceinline__ void st_plane(char *base, unsigned off, float x, unsigned key,
+                                         typename Conv<S>::Reg &r) {
+    gstore(base, off, Conv<S>::bits(x, key, r));
 }
 __device__ __forceinline__ float lag_plane(const char *base, unsigned off) {
     const LagT v = __builtin_bit_cast(LagT, gload<unsigned short>(base, off));
@@ -727,12 +732,13 @@ __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A,
     // an offset it sees widened from 32 bits in the same block.
     unsigned so = o, so2 = o2, so4 = o4;
     asm volatile("" : "+v"(so), "+v"(so2), "+v"(so4));
+    typename Conv<S>::Reg r{};
 #pragma unroll
-    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], so, f[q], skey(i, j, q));
+    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], so, f[q], skey(i, j, q), r);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        st_plane<S>(A.wr[GOFF + q], so, g[q], skey(i, j, GOFF + q));
-        st_plane<S>(A.wr[HOFF + q], so, h[q], skey(i, j, HOFF + q));
+        st_plane<S>(A.wr[GOFF + q], so, g[q], skey(i, j, GOFF + q), r);
+        st_plane<S>(A.wr[HOFF + q], so, h[q], skey(i, j, HOFF + q), r);
     }
     gstore(A.lwr[0], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.ux * LAG_SCALE)));
     gstore(A.lwr[1], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.uy * LAG_SCALE)));
