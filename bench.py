@@ -201,6 +201,9 @@ def main():
     ap.add_argument("--Nz", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=30,
                     help="steps of the oracle on the benchmark lattice (~15 s on one core)")
+    ap.add_argument("--u-noise", type=float, default=1e-4,
+                    help="seeded velocity noise of the initial state (0: at rest, so that "
+                         "the swirl populations stay exactly zero away from the lid)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="step-kernel tile shape; -1: autotune on the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -247,7 +250,8 @@ def main():
     from paper_1806_10241_amd import axlb
     from paper_1806_10241_amd import inputs as I
 
-    case = I.rotating_lid_cylinder(Nr=args.Nr, Nz=args.Nz, Re=1000.0, Ri=0.5)
+    case = I.rotating_lid_cylinder(Nr=args.Nr, Nz=args.Nz, Re=1000.0, Ri=0.5,
+                                   u_noise=args.u_noise)
     nodes = case["Nr"] * case["Nz"]
     stream = torch.cuda.Stream()
     lat = axlb.Lattice(case, storage=args.storage, layout=args.layout, stream=stream,
@@ -301,6 +305,7 @@ def main():
         "dtype": "f32" if args.storage == "f32" else "f32-compute/%s-storage" % args.storage,
         "data": "synthetic",
         "config": {"workload": "rotating-lid cylinder with buoyancy, Re=1000, Ri=0.5, Pr=1",
+                   "initial_noise": {"T": 1e-4, "u": args.u_noise},
                    "Nr": args.Nr, "Nz": args.Nz, "storage": args.storage,
                    "layout": args.layout, "derivatives": args.deriv,
                    "graph_bundle": 0 if args.single_launches else 100,

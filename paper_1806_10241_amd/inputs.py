@@ -90,10 +90,20 @@ def convection_velocity_scale_params(L: float, Pr: float, Ra: float, U: float = 
     return nu, alpha, Ra_eff
 
 
-def _perturbed_T(seed: int, Nz: int, Nr: int, base: float = 0.5, amp: float = 1e-4):
+def _perturbed_T(seed: int, Nz: int, Nr: int, base: float = 0.5, amp: float = 1e-4,
+                 u_amp: float = 0.0):
+    """T = base + seeded uniform noise of amplitude amp; with u_amp > 0 also
+    u_r, u_z, u_theta = seeded uniform noise of amplitude u_amp (streams
+    offset from the temperature's, so every field draws its own numbers)."""
     def make():
-        T = base + amp * (2.0 * uniform(seed, Nz * Nr) - 1.0)
-        return {"T": T.reshape(Nz, Nr)}
+        N = Nz * Nr
+        T = base + amp * (2.0 * uniform(seed, N) - 1.0)
+        out = {"T": T.reshape(Nz, Nr)}
+        if u_amp > 0.0:
+            for k, name in enumerate(("ur", "uz", "uth")):
+                u = u_amp * (2.0 * uniform(seed, N, offset=(k + 1) * N) - 1.0)
+                out[name] = u.reshape(Nz, Nr)
+        return out
     return make
 
 
@@ -138,13 +148,15 @@ def annulus_convection(Nr: int = 256, Nz: int = 256, radius_ratio: float = 2.0,
 
 def rotating_lid_cylinder(Nr: int = 1024, Nz: int = 2048, Re: float = 1000.0,
                           Ri: float = 0.5, Pr: float = 1.0, u_lid: float = 0.05,
-                          seed: int = 3) -> dict:
+                          seed: int = 3, u_noise: float = 0.0) -> dict:
     """Closed cylinder H = Nz, R = Nr with a rotating bottom lid (u_theta =
     Omega r, Omega R = u_lid), Re = Omega R^2 / nu, axial temperature
     difference (top T = 1, bottom T = 0, adiabatic side wall) with
     Richardson number Ri = g beta dT R / (Omega R)^2, Pr = nu / alpha
     (Section 3.4 geometry with the buoyancy of Section 3.3).  The axis uses
-    the mirror condition."""
+    the mirror condition.  u_noise > 0 adds seeded velocity noise of that
+    amplitude to the initial rest state (every population then differs from
+    its rest value from the first step on)."""
     R = float(Nr)
     Omega = u_lid / R
     nu = u_lid * R / Re
@@ -159,7 +171,7 @@ def rotating_lid_cylinder(Nr: int = 1024, Nz: int = 2048, Re: float = 1000.0,
     return dict(name="rotating_lid_cylinder", Nr=Nr, Nz=Nz, cylinder=1, r_inner=0.0,
                 nu=nu, alpha=alpha, Pr=Pr, Ra=Ra, Re=Re, Ri=Ri, Omega=Omega,
                 g_axial=0.0, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5, seed=seed,
-                fields=_perturbed_T(seed, Nz, Nr))
+                fields=_perturbed_T(seed, Nz, Nr, u_amp=u_noise))
 
 
 def rayleigh_benard_cylinder(Nr: int = 100, Nz: int = 100, Pr: float = 0.7, Ra: float = 5e3,
