@@ -50,6 +50,11 @@ def test_state_bytes_and_argument_checks():
     rc = lib.axlb_lattice_create(32, 8, C.byref(geo), 0.1, 0.1, 0.7, 0.0, 0.0, None, None,
                                  C.byref(out))
     assert rc == axlb.EINVAL  # Pr != nu/alpha
+    # a plane of more than 2^30 nodes (rows padded to 64) exceeds the 32-bit
+    # byte offsets of the step kernel; exactly 2^30 is accepted by the check
+    rc = lib.axlb_lattice_create(1000, (1 << 20) + 1, C.byref(geo), 0.1, 0.1, 0.0, 0.0, 0.0,
+                                 None, None, C.byref(out))
+    assert rc == axlb.EINVAL and b"2^30" in lib.axlb_last_error(None)
 
 
 def test_current_derivatives_rejected_with_one_buffer():
