@@ -29,7 +29,9 @@ namespace axlb {
 // so that the hardware deals them to all eight XCDs and the tiles after
 // them keep their XCD alignment), and the tile workgroups skip the edge
 // nodes; the AA even phase streams within each node's own slots, so its
-// tiles take every node.  Tile workgroups are XCD-remapped as in tile_of.
+// tiles take every node.  Tile workgroups are XCD-remapped as in tile_of
+// and reach every value through the launch's plane addresses (Planes); edge
+// workgroups take the general per-node path.
 template <class S, int MODE, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const Planes A,
                                                    const S *src, S *dst,
