@@ -14,6 +14,19 @@
 
 namespace axlb {
 
+// Pull of node (i, j): through the plane addresses when every source is a
+// fluid node, else with the boundary rules.
+template <class S>
+__device__ __forceinline__ void pull_node(const KParams &P, const Planes &A, const S *src, int i,
+                                          int j, bool interior, float (&f)[9], float (&g)[5],
+                                          float (&h)[5]) {
+    if (interior)
+        gather_planes<S>(A, ((unsigned)i * (unsigned)P.pitch + (unsigned)j) * (unsigned)sizeof(S),
+                         f, g, h);
+    else
+        gather<S, MODE_AB>(P, src, i, j, false, f, g, h);
+}
+
 // Output fields of a node into the LDS tile F[4][H][W] at (a, b).
 template <int H, int W>
 __device__ __forceinline__ void put_fields(float (&F)[4][H][W], int a, int b, const Moments &m) {
@@ -28,8 +41,8 @@ __device__ __forceinline__ void put_fields(float (&F)[4][H][W], int a, int b, co
 // cell (a, b); positions outside the fluid that are not a periodic image are
 // left alone (their ghosts come from the wall and axis rules).
 template <class S, int H, int W>
-__device__ __forceinline__ void fill_cell(const KParams &P, const S *src, float (&F)[4][H][W],
-                                          int a, int b, int i, int j) {
+__device__ __forceinline__ void fill_cell(const KParams &P, const Planes &A, const S *src,
+                                          float (&F)[4][H][W], int a, int b, int i, int j) {
     if ((unsigned)j >= (unsigned)P.Nr) return;
     if ((unsigned)i >= (unsigned)P.Nz) {
         if (kind_of(P, i < 0 ? Z_LO : Z_HI, FLOW) != PERIODIC) return;
@@ -37,13 +50,14 @@ __device__ __forceinline__ void fill_cell(const KParams &P, const S *src, float 
         if ((unsigned)i >= (unsigned)P.Nz) return;
     }
     float f[9], g[5], h[5];
-    gather<S, MODE_AB>(P, src, i, j, interior_node(P, i, j), f, g, h);
+    pull_node<S>(P, A, src, i, j, interior_node(P, i, j), f, g, h);
     put_fields(F, a, b, moments(f, g, h));
 }
 
 // One step (STEP) or the reported fields (!STEP) of every node.
 template <class S, int BX, int BY, bool STEP>
-__global__ void __launch_bounds__(BX * BY) k_current(const KParams P, const S *src, S *dst,
+__global__ void __launch_bounds__(BX * BY) k_current(const KParams P, const Planes A,
+                                                      const S *src, S *dst,
                                                       double *__restrict__ out) {
     constexpr int W = BX + 2, H = BY + 2, RING = 2 * BX + 2 * BY;
     __shared__ float F[4][H][W];
@@ -56,11 +70,11 @@ __global__ void __launch_bounds__(BX * BY) k_current(const KParams P, const S *s
     float f[9], g[5], h[5];
     Moments m{};
     if (live) {
-        gather<S, MODE_AB>(P, src, i, j, interior, f, g, h);
+        pull_node<S>(P, A, src, i, j, interior, f, g, h);
         m = moments(f, g, h);
         put_fields(F, ty + 1, tx + 1, m);
     } else {
-        fill_cell<S>(P, src, F, ty + 1, tx + 1, i, j);  // periodic image beyond the domain
+        fill_cell<S>(P, A, src, F, ty + 1, tx + 1, i, j);  // periodic image beyond the domain
     }
     // the ring without its corners (the differences only look along the
     // axes): rows 0 and H-1, then columns 0 and W-1
@@ -74,7 +88,7 @@ __global__ void __launch_bounds__(BX * BY) k_current(const KParams P, const S *s
             a = 1 + (u >> 1);
             b = (u & 1) ? W - 1 : 0;
         }
-        fill_cell<S>(P, src, F, a, b, i0 - 1 + a, j0 - 1 + b);
+        fill_cell<S>(P, A, src, F, a, b, i0 - 1 + a, j0 - 1 + b);
     }
     __syncthreads();
     if (!live) return;
@@ -86,7 +100,12 @@ __global__ void __launch_bounds__(BX * BY) k_current(const KParams P, const S *s
         collide_f(P, f, Hs);
         collide_adv(g, Hs.ux, Hs.uy, Hs.psi, Hs.psi, Hs.hSpsi, P.og12, P.og3, P.og4);
         collide_adv(h, Hs.ux, Hs.uy, P.Tref + Hs.dphi, Hs.dphi, Hs.hSphi, P.oh12, P.oh3, P.oh4);
-        scatter<S, MODE_AB>(P, dst, i, j, interior, f, g, h);
+        if (interior)
+            scatter_planes<S>(A, local_offset(((unsigned)i * (unsigned)P.pitch + (unsigned)j) *
+                                              (unsigned)sizeof(S)),
+                              i, j, f, g, h);
+        else
+            scatter<S, MODE_AB>(P, dst, i, j, false, f, g, h);
     } else {
         const long long N = (long long)P.Nr * P.Nz, k = (long long)i * P.Nr + j;
         out[k] = 1.0 + (double)Hs.drho;
@@ -102,11 +121,13 @@ static hipError_t step_current_t(const KParams &P, int tile, const void *src, vo
                                  hipStream_t st) {
     const S *a = (const S *)src;
     S *b = (S *)dst;
+    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, MODE_AB, src, dst,
+                                 nullptr, nullptr);
     switch (tile) {
 #define AXLB_CASE(id, bx, by)                                                                 \
     case id:                                                                                  \
         k_current<S, bx, by, true><<<dim3(((P.Nr + bx - 1) / bx) * ((P.Nz + by - 1) / by)), \
-                                     dim3(bx * by), 0, st>>>(P, a, b, nullptr);               \
+                                     dim3(bx * by), 0, st>>>(P, A, a, b, nullptr);            \
         break;
         AXLB_TILES(AXLB_CASE)
 #undef AXLB_CASE
@@ -117,8 +138,11 @@ static hipError_t step_current_t(const KParams &P, int tile, const void *src, vo
 
 template <class S>
 static hipError_t fields_current_t(const KParams &P, const void *src, double *out, hipStream_t st) {
+    // reads only: the write planes are never used
+    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, MODE_AB, src,
+                                 const_cast<void *>(src), nullptr, nullptr);
     k_current<S, 64, 4, false><<<dim3(((P.Nr + 63) / 64) * ((P.Nz + 3) / 4)), dim3(256), 0, st>>>(
-        P, (const S *)src, nullptr, out);
+        P, A, (const S *)src, nullptr, out);
     return hipGetLastError();
 }
 

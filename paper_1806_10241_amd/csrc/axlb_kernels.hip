@@ -293,12 +293,15 @@ Planes step_planes(const KParams &P, int storage, int mode, const void *src, voi
         plane_offsets<THERMAL>(P, mode, q, rd, wr);
         set(HOFF + q, rd, wr);
     }
-    for (int v = 0; v < NLAG; ++v) {
-        A.lrd[v] = (const char *)(Mprev + v * P.plane);
-        A.lwr[v] = (char *)(Mnext + v * P.plane);
+    // the lagged-field planes (left null for launches without them)
+    if (Mprev && Mnext) {
+        for (int v = 0; v < NLAG; ++v) {
+            A.lrd[v] = (const char *)(Mprev + v * P.plane);
+            A.lwr[v] = (char *)(Mnext + v * P.plane);
+        }
+        A.uy_up = (const char *)((uintptr_t)A.lrd[1] + (uintptr_t)(2 * P.pitch));
+        A.uy_dn = (const char *)((uintptr_t)A.lrd[1] - (uintptr_t)(2 * P.pitch));
     }
-    A.uy_up = (const char *)((uintptr_t)A.lrd[1] + (uintptr_t)(2 * P.pitch));
-    A.uy_dn = (const char *)((uintptr_t)A.lrd[1] - (uintptr_t)(2 * P.pitch));
     return A;
 }
 

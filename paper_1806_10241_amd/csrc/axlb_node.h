@@ -703,12 +703,12 @@ __device__ __forceinline__ float lag_plane(const char *base, unsigned off) {
 // AA odd phase and the two-buffer pull.  The arithmetic, the rounding keys
 // and the derivative stencils are update_node's, so both give identical
 // bits; only the address arithmetic differs (one 32-bit offset per node).
+// The 19 populations node (i, j) reads (gather_planes) or writes
+// (scatter_planes) through plane addresses; o is the node's byte offset
+// n * sizeof(S).
 template <class S>
-__device__ __forceinline__ void update_planes(const KParams &P, const Planes &A, int i, int j,
-                                              bool interior) {
-    const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
-    const unsigned o = n * (unsigned)sizeof(S), o2 = n * 2u, o4 = n * 4u;
-    float f[9], g[5], h[5];
+__device__ __forceinline__ void gather_planes(const Planes &A, unsigned o, float (&f)[9],
+                                              float (&g)[5], float (&h)[5]) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) f[q] = ld_plane<S>(A.rd[q], o);
 #pragma unroll
@@ -716,6 +716,35 @@ __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A,
         g[q] = ld_plane<S>(A.rd[GOFF + q], o);
         h[q] = ld_plane<S>(A.rd[HOFF + q], o);
     }
+}
+template <class S>
+__device__ __forceinline__ void scatter_planes(const Planes &A, unsigned o, int i, int j,
+                                               const float (&f)[9], const float (&g)[5],
+                                               const float (&h)[5]) {
+    typename Conv<S>::Reg r{};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], o, f[q], skey(i, j, q), r);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        st_plane<S>(A.wr[GOFF + q], o, g[q], skey(i, j, GOFF + q), r);
+        st_plane<S>(A.wr[HOFF + q], o, h[q], skey(i, j, HOFF + q), r);
+    }
+}
+// A register copy of a byte offset that the compiler cannot trace back to
+// an earlier basic block: it chooses the SGPR-base address form per block,
+// only for an offset it sees widened from 32 bits in the same block.
+__device__ __forceinline__ unsigned local_offset(unsigned o) {
+    asm volatile("" : "+v"(o));
+    return o;
+}
+
+template <class S>
+__device__ __forceinline__ void update_planes(const KParams &P, const Planes &A, int i, int j,
+                                              bool interior) {
+    const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+    const unsigned o = n * (unsigned)sizeof(S), o2 = n * 2u, o4 = n * 4u;
+    float f[9], g[5], h[5];
+    gather_planes<S>(A, o, f, g, h);
     float d[5];
     if (interior) {
         d[0] = 0.5f * (lag_plane(A.uy_up, o2) - lag_plane(A.uy_dn, o2));
@@ -727,19 +756,9 @@ __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A,
         differences(P, LagSource{P, reinterpret_cast<const LagT *>(A.lrd[0]), i, j}, i, j, d);
     }
     const Half H = relax_node(P, j, f, g, h, d);
-    // Register copies of the offsets, made after the branch above: the
-    // compiler chooses the SGPR-base address form per basic block, only for
-    // an offset it sees widened from 32 bits in the same block.
-    unsigned so = o, so2 = o2, so4 = o4;
-    asm volatile("" : "+v"(so), "+v"(so2), "+v"(so4));
-    typename Conv<S>::Reg r{};
-#pragma unroll
-    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], so, f[q], skey(i, j, q), r);
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        st_plane<S>(A.wr[GOFF + q], so, g[q], skey(i, j, GOFF + q), r);
-        st_plane<S>(A.wr[HOFF + q], so, h[q], skey(i, j, HOFF + q), r);
-    }
+    // the stores follow the branch above
+    const unsigned so = local_offset(o), so2 = local_offset(o2), so4 = local_offset(o4);
+    scatter_planes<S>(A, so, i, j, f, g, h);
     gstore(A.lwr[0], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.ux * LAG_SCALE)));
     gstore(A.lwr[1], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.uy * LAG_SCALE)));
     gstore(A.lwr[2], so2,

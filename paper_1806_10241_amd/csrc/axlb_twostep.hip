@@ -10,6 +10,8 @@
 // step t + 1 from LDS alone and writes the state after t + 1.  The per-node
 // arithmetic is the single-step kernels' (axlb_node.h), so the result equals
 // two single steps bit for bit, while the state crosses HBM once per pair.
+// Interior cells read, and the tile writes, through the plane addresses of
+// a two-buffer pull (Planes).
 #include "axlb_device.h"
 #include "axlb_launch.h"
 #include "axlb_node.h"
@@ -30,7 +32,8 @@ struct TilePops {
 };
 
 template <class S, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const S *src, S *dst,
+__global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Planes A,
+                                                       const S *src, S *dst,
                                                        const LagT *__restrict__ Mprev,
                                                        LagT *__restrict__ Mnext) {
     constexpr int W = BX + 2, H = BY + 2, NC = W * H;
@@ -54,7 +57,11 @@ __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const S *
         }
         const bool interior = interior_node(P, ci, cj);
         float f[9], g[5], h[5], d[5];
-        gather<S, MODE_AB>(P, src, ci, cj, interior, f, g, h);
+        if (interior)
+            gather_planes<S>(A, ((unsigned)ci * (unsigned)P.pitch + (unsigned)cj) *
+                                    (unsigned)sizeof(S), f, g, h);
+        else
+            gather<S, MODE_AB>(P, src, ci, cj, false, f, g, h);
         derivatives(P, Mprev, ci, cj, interior, d);
         const Half Hs = relax_node(P, cj, f, g, h, d);
 #pragma unroll
@@ -77,8 +84,8 @@ __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const S *
     pull_all<false>(P, TilePops<S, H, W>{pop, i0, j0}, i, j, f, g, h);
     differences(P, TileSource<H, W>{lag, ty + 1, tx + 1}, i, j, d);
     const Half Hs = relax_node(P, j, f, g, h, d);
-    scatter<S, MODE_AB>(P, dst, i, j, false, f, g, h);
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+    scatter_planes<S>(A, local_offset(n * (unsigned)sizeof(S)), i, j, f, g, h);
     lag_st(Mnext, 0, P.plane, n, Hs.ux);
     lag_st(Mnext, 1, P.plane, n, Hs.uy);
     lag_st(Mnext, 2, P.plane, n, Hs.psi * Hs.irho);
@@ -89,8 +96,10 @@ template <class S>
 static hipError_t step_two_t(const KParams &P, const void *src, void *dst, const LagT *Mprev,
                              LagT *Mnext, hipStream_t st) {
     const int gx = (P.Nr + TWO_BX - 1) / TWO_BX, gy = (P.Nz + TWO_BY - 1) / TWO_BY;
+    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, MODE_AB, src, dst,
+                                 Mprev, Mnext);
     k_step_two<S, TWO_BX, TWO_BY><<<dim3(gx * gy), dim3(TWO_BX * TWO_BY), 0, st>>>(
-        P, (const S *)src, (S *)dst, Mprev, Mnext);
+        P, A, (const S *)src, (S *)dst, Mprev, Mnext);
     return hipGetLastError();
 }
 
