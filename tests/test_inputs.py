@@ -54,3 +54,19 @@ def test_batched_and_served_recipes():
     for _, c, st in trace[:200]:
         assert c["Nr"] % 16 == 0 and c["Nz"] % 16 == 0 and 64 <= c["Nr"] <= 1024
         assert st in ("f32", "f16")
+
+
+def test_rotating_lid_velocity_noise():
+    """u_noise seeds u_r, u_z, u_theta from streams of their own (disjoint
+    from the temperature's), within the amplitude; the default is a rest
+    state with temperature noise only."""
+    quiet = I.rotating_lid_cylinder(Nr=64, Nz=32)["fields"]()
+    assert sorted(quiet) == ["T"]
+    f = I.rotating_lid_cylinder(Nr=64, Nz=32, u_noise=1e-4)["fields"]()
+    assert sorted(f) == ["T", "ur", "uth", "uz"]
+    assert np.array_equal(f["T"], quiet["T"])
+    for k in ("ur", "uz", "uth"):
+        assert f[k].shape == (32, 64) and np.abs(f[k]).max() <= 1e-4 and np.abs(f[k]).min() > 0
+    # independent draws: no two fields share a value pattern
+    assert not np.allclose(f["ur"], f["uz"]) and not np.allclose(f["uz"], f["uth"])
+    assert abs(np.corrcoef(f["ur"].ravel(), (f["T"] - 0.5).ravel())[0, 1]) < 0.1
