@@ -242,9 +242,10 @@ int axlb_halo_import(axlb_lattice *lat, int face, const void *device_src);
  * A batch advances all its member lattices together: a step of many members
  * is one fused launch over a work-list of (member, tile) entries, and
  * 100-step bundles are captured as HIP graphs.  Within a bundle, runs of
- * consecutive members whose states total at most 160 MB (below the 256 MB
- * Infinity Cache) take all 100 steps before the next run starts; after
- * axlb_batch_step every member has advanced by the same count either way.
+ * consecutive members whose states total at most 80 MB take all 100 steps
+ * before the next run starts, two runs at a time on two streams (together
+ * below the 256 MB Infinity Cache); after axlb_batch_step every member has
+ * advanced by the same count either way.
  * Members must share device
  * and storage, use the AA layout and belong to no other batch; their
  * boundary rules are locked.  While batched, a member runs on the batch's

@@ -2,10 +2,12 @@
 // many members runs as one fused launch over a work-list of (member, tile)
 // pairs (chunks of a member's edge nodes, then its tiles).  100-step bundles
 // are captured as HIP graphs; within a bundle, consecutive members whose
-// state fits the Infinity Cache together form a group that takes all 100
-// steps before the next group starts, so the state of the running group
-// stays in that cache (the members are independent, so their steps need no
-// common order).  The tile shape and the launch schedule come from an
+// state fits half the Infinity Cache together form a group that takes all
+// 100 steps before the next group of its chain starts, and groups alternate
+// between two chains (streams) that run side by side, so the states of the
+// two running groups stay in that cache and one group's launch ramp and
+// tail overlap the other's work (the members are independent, so their
+// steps need no common order).  The tile shape and the launch schedule come from an
 // autotuner.  The node update is the one of the single-lattice kernels
 // (axlb_node.h), so a member's result does not depend on whether it ran
 // alone or in a batch.
@@ -23,9 +25,10 @@
 
 namespace axlb {
 
-// State bytes of the members that one group holds: below MI355X's 256 MB
-// Infinity Cache, with room for the other traffic of a step.
-constexpr size_t GROUP_BYTES = 160u << 20;
+// State bytes of the members that one group holds: two groups run at once,
+// together below MI355X's 256 MB Infinity Cache with room for the other
+// traffic of a step.
+constexpr size_t GROUP_BYTES = 80u << 20;
 
 // Per-member descriptor in device memory.
 struct InstDesc {
@@ -112,6 +115,11 @@ using namespace axlb;
 struct axlb_batch {
     int device = 0;
     hipStream_t stream = nullptr;
+    // a bundle runs its groups on two chains, the batch stream and `side`,
+    // forked and joined by these events, so that two groups share the
+    // device and one group's launch ramp and tail overlap the other's work
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     std::vector<axlb_lattice *> members;
     std::vector<hipStream_t> member_streams;
     int storage = 0;
@@ -201,16 +209,19 @@ static int build_worklist(axlb_batch *b) {
 }
 
 // One step (parity s & 1) of the work-list entries [t0, t1).
-static int batch_launch(axlb_batch *b, long s, int t0, int t1) {
+static int batch_launch(axlb_batch *b, long s, int t0, int t1, hipStream_t st) {
     const int n = t1 - t0;
     int blocks = b->blocks > 0 ? b->blocks : n;
     if (blocks < 8) blocks = 8;  // every XCD chunk needs a block
     hipError_t e = launch_batch(b->storage, b->tile, blocks, b->d_desc, b->d_tiles, t0, n,
-                                (int)(s & 1), b->stream);
+                                (int)(s & 1), st);
     if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     return AXLB_OK;
 }
 
+static int batch_launch(axlb_batch *b, long s, int t0, int t1) {
+    return batch_launch(b, s, t0, t1, b->stream);
+}
 static int batch_launch(axlb_batch *b, long s) { return batch_launch(b, s, 0, b->ntiles); }
 
 static void advance_members(axlb_batch *b, long n) {
@@ -240,7 +251,14 @@ int axlb_batch_create(axlb_lattice *const *lats, int n, axlb_batch **out) {
     b->device = dev;
     b->storage = lats[0]->storage;
     if (hipSetDevice(dev) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+        if (b->join) (void)hipEventDestroy(b->join);
+        if (b->fork) (void)hipEventDestroy(b->fork);
+        if (b->side) (void)hipStreamDestroy(b->side);
+        if (b->stream) (void)hipStreamDestroy(b->stream);
         delete b;
         return bfail(nullptr, AXLB_EDEVICE, "stream creation failed");
     }
@@ -306,12 +324,20 @@ int axlb_batch_step(axlb_batch *b, long n) {
             const int k = (int)(b->steps & 1);
             if (!b->graph[k]) {
                 BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-                // group by group: each group's state stays in the Infinity
-                // Cache for the whole bundle
+                // group by group, alternate groups on two chains: each
+                // group's state stays in the Infinity Cache for the whole
+                // bundle, and two groups run side by side
                 int rc = AXLB_OK;
+                hipError_t fe = hipEventRecord(b->fork, b->stream);
+                if (fe == hipSuccess) fe = hipStreamWaitEvent(b->side, b->fork, 0);
+                if (fe != hipSuccess) rc = bfail(b, AXLB_EDEVICE, "batch graph fork failed");
                 for (size_t g = 0; g + 1 < b->group.size() && rc == AXLB_OK; ++g)
                     for (long s = 0; s < BUNDLE && rc == AXLB_OK; ++s)
-                        rc = batch_launch(b, k + s, b->group[g], b->group[g + 1]);
+                        rc = batch_launch(b, k + s, b->group[g], b->group[g + 1],
+                                          g % 2 ? b->side : b->stream);
+                fe = hipEventRecord(b->join, b->side);
+                if (fe == hipSuccess) fe = hipStreamWaitEvent(b->stream, b->join, 0);
+                if (fe != hipSuccess && rc == AXLB_OK) rc = bfail(b, AXLB_EDEVICE, "batch graph join failed");
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(b->stream, &g);
                 if (rc != AXLB_OK) {
@@ -433,6 +459,9 @@ void axlb_batch_destroy(axlb_batch *b) {
     }
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->join) (void)hipEventDestroy(b->join);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->side) (void)hipStreamDestroy(b->side);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
