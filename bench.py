@@ -32,12 +32,23 @@ STEP_SOURCES = ["paper_1806_10241_amd/csrc/axlb_node.h", "paper_1806_10241_amd/c
                 "paper_1806_10241_amd/csrc/axlb_device.h"]
 
 
+def code_text(source: bytes) -> bytes:
+    """A C++ source without its comments and with whitespace runs collapsed,
+    so that edits to comments alone keep a counter summary valid."""
+    import re
+    text = source.decode()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split()).encode()
+
+
 def step_kernel_hash() -> str:
+    """sha256 of the code (comments excluded) of the step-kernel sources."""
     import hashlib
     h = hashlib.sha256()
     for rel in STEP_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+            h.update(code_text(f.read()))
     return h.hexdigest()
 
 

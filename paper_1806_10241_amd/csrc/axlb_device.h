@@ -105,21 +105,9 @@ __device__ __forceinline__ float val_of(const KParams &P, int face) {
 }
 
 // Storage conversions: FP32 arithmetic; FP32, binary16 or bfloat16 storage.
-// The 16-bit stores round stochastically: noise below the target precision
-// is added to the FP32 bit pattern before truncation, so that increments
-// smaller than half a 16-bit ulp survive in expectation instead of being
-// rounded away every step.  The noise is a hash of the FP32 value and of the
-// slot key, hence deterministic (reruns and checkpoints are bitwise
-// reproducible) and fresh whenever the value changes.
-__device__ __forceinline__ unsigned mix32(unsigned x) {
-    x ^= x >> 16;
-    x *= 0x7feb352dU;
-    x ^= x >> 15;
-    x *= 0x846ca68bU;
-    x ^= x >> 16;
-    return x;
-}
-
+// The 16-bit stores round stochastically, so that increments smaller than
+// half a 16-bit ulp survive in expectation instead of being rounded away
+// every step (see the 16-bit specialisations below).
 template <class S> struct Conv;
 // Conv<S>::bits(v, key, r) gives the bit pattern st stores for v; the
 // 16-bit conversions write it into the low half of the register r and leave
