@@ -35,7 +35,13 @@ __device__ __forceinline__ const float *lag_T(const LagT *M, long long plane) {
 __device__ __forceinline__ float *lag_T(LagT *M, long long plane) {
     return reinterpret_cast<float *>(M + 3 * plane);
 }
-__device__ __forceinline__ float lag_h(const LagT *p) { return __half2float(*p) * (1.f / LAG_SCALE); }
+// Scaled binary16 -> FP32 as one mixed-precision FMA (v_fma_mix_f32: the
+// binary16 operand is widened inside the instruction); adding +0 instead of
+// multiplying only turns a -0 result into +0.
+__device__ __forceinline__ float f16_scaled(__half h, float s) {
+    return __builtin_fmaf(__half2float(h), s, 0.f);
+}
+__device__ __forceinline__ float lag_h(const LagT *p) { return f16_scaled(*p, 1.f / LAG_SCALE); }
 // Field v at element offset off of a block with the given plane size.
 template <class I>
 __device__ __forceinline__ float lag_ld(const LagT *M, int v, long long plane, I off) {
@@ -50,7 +56,7 @@ __device__ __forceinline__ void lag_st(LagT *M, int v, long long plane, I off, f
 // The value lag_ld returns after lag_st stored x in field v.
 __device__ __forceinline__ float lag_round(int v, float x) {
     if (v == 3) return x;
-    return __half2float(__float2half_rn(x * LAG_SCALE)) * (1.f / LAG_SCALE);
+    return f16_scaled(__float2half_rn(x * LAG_SCALE), 1.f / LAG_SCALE);
 }
 
 // Everything a step kernel needs, passed by value.
@@ -141,7 +147,7 @@ constexpr float F16_SCALE = 256.f;
 template <> struct Conv<__half> {
     using Reg = half2_t;
     __device__ static __forceinline__ float ld(const __half *p) {
-        return __half2float(*p) * (1.f / F16_SCALE);
+        return f16_scaled(*p, 1.f / F16_SCALE);
     }
     __device__ static __forceinline__ unsigned short bits(float v, unsigned key, Reg &r) {
         const float x = v * F16_SCALE;
