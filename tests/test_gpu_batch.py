@@ -43,6 +43,27 @@ def test_batch_equals_alone(gpu, storage):
     b.close()
 
 
+def test_cache_groups_on_two_streams_equal_alone(gpu):
+    """Members whose states exceed one cache group: a bundle splits them into
+    groups that alternate between two streams; every member still ends
+    bit-identical to stepping alone (two bundles and a partial one)."""
+    say("batch groups on two streams")
+    from paper_1806_10241_amd import axlb
+    cases = [I.annulus_convection(Nr=640, Nz=512, Ra=10 ** (3 + 0.4 * k), seed=70 + k)
+             for k in range(6)]
+    assert sum(axlb.state_bytes(c["Nr"], c["Nz"]) for c in cases) > 3 * (80 << 20) // 2
+    alone = [axlb.Lattice(c) for c in cases]
+    batched = [axlb.Lattice(c) for c in cases]
+    b = axlb.Batch(batched)
+    b.step(237)
+    b.sync()
+    for lat in alone:
+        lat.step(237)
+    for la, lb in zip(alone, batched):
+        assert la.save() == lb.save()
+    b.close()
+
+
 def test_batch_autotune_restores_state_and_members_are_locked(gpu):
     say("batch autotune")
     from paper_1806_10241_amd import axlb
