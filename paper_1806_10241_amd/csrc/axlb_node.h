@@ -697,12 +697,6 @@ __device__ __forceinline__ float lag_plane(const char *base, unsigned off) {
     return lag_h(&v);
 }
 
-// The same update through a launch's plane addresses (Planes), for the tile
-// workgroups of the step kernel: valid for every node in the AA even phase
-// (each node reads and writes its own slots) and for interior nodes in the
-// AA odd phase and the two-buffer pull.  The arithmetic, the rounding keys
-// and the derivative stencils are update_node's, so both give identical
-// bits; only the address arithmetic differs (one 32-bit offset per node).
 // The 19 populations node (i, j) reads (gather_planes) or writes
 // (scatter_planes) through plane addresses; o is the node's byte offset
 // n * sizeof(S).
@@ -738,6 +732,12 @@ __device__ __forceinline__ unsigned local_offset(unsigned o) {
     return o;
 }
 
+// The same update through a launch's plane addresses (Planes), for the tile
+// workgroups of the step kernel: valid for every node in the AA even phase
+// (each node reads and writes its own slots) and for interior nodes in the
+// AA odd phase and the two-buffer pull.  The arithmetic, the rounding keys
+// and the derivative stencils are update_node's, so both give identical
+// bits; only the address arithmetic differs (one 32-bit offset per node).
 template <class S>
 __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A, int i, int j,
                                               bool interior) {
