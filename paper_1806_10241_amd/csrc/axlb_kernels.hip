@@ -23,12 +23,17 @@
 
 namespace axlb {
 
+// Edge nodes per edge workgroup: one wavefront's worth whatever the tile
+// shape, so that the slow, uncoalesced boundary code is spread over more
+// compute units (the other wavefronts of an edge workgroup exit at once).
+constexpr int EDGE_PER_BLOCK = 64;
+
 // One time step for every node of one lattice.  Where boundary rules apply
-// to the streaming (AA odd phase, AB), the first workgroups take BX * BY
-// consecutive edge nodes each (their count rounded up to a multiple of 8,
-// so that the hardware deals them to all eight XCDs and the tiles after
-// them keep their XCD alignment), and the tile workgroups skip the edge
-// nodes; the AA even phase streams within each node's own slots, so its
+// to the streaming (AA odd phase, AB), the first workgroups take
+// EDGE_PER_BLOCK consecutive edge nodes each (their count rounded up to a
+// multiple of 8, so that the hardware deals them to all eight XCDs and the
+// tiles after them keep their XCD alignment), and the tile workgroups skip
+// the edge nodes; the AA even phase streams within each node's own slots, so its
 // tiles take every node.  Tile workgroups are XCD-remapped as in tile_of
 // and reach every value through the launch's plane addresses (Planes); edge
 // workgroups take the general per-node path.
@@ -39,10 +44,11 @@ __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const Planes 
                                                    LagT *__restrict__ Mnext) {
     constexpr bool SPLIT = MODE != MODE_AA_EVEN;
     const int gx = (P.Nr + BX - 1) / BX;
-    const int ne = SPLIT ? edge_blocks(P.Nr, P.Nz, BX * BY) : 0;
+    const int ne = SPLIT ? edge_blocks(P.Nr, P.Nz, EDGE_PER_BLOCK) : 0;
     const int b = (int)blockIdx.x;
     if (SPLIT && b < ne) {
-        const int e = b * (BX * BY) + (int)threadIdx.x;
+        if ((int)threadIdx.x >= EDGE_PER_BLOCK) return;
+        const int e = b * EDGE_PER_BLOCK + (int)threadIdx.x;
         if (e >= edge_count(P.Nr, P.Nz)) return;
         int i, j;
         edge_node(P, e, i, j);
@@ -308,7 +314,7 @@ Planes step_planes(const KParams &P, int storage, int mode, const void *src, voi
 template <class S, int BX, int BY>
 static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT *Mprev,
                              LagT *Mnext, hipStream_t st) {
-    const int edges = mode == MODE_AA_EVEN ? 0 : edge_blocks(P.Nr, P.Nz, BX * BY);
+    const int edges = mode == MODE_AA_EVEN ? 0 : edge_blocks(P.Nr, P.Nz, EDGE_PER_BLOCK);
     const dim3 grid(grid_for(P, BX, BY).x + edges), block(BX * BY);
     const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, mode, a,
                                  mode == MODE_AB ? b : a, Mprev, Mnext);
