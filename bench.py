@@ -229,7 +229,7 @@ def main():
     ap.add_argument("--serve-max-nr-log2", type=float, default=10.0)
     ap.add_argument("--serve-max-nz-log2", type=float, default=11.0)
     ap.add_argument("--serve-order", default="smallest", choices=["smallest", "fifo"])
-    ap.add_argument("--serve-window", type=int, default=2 << 20,
+    ap.add_argument("--serve-window", type=int, default=4 << 20,
                     help="cap on resident fluid nodes in the pool (0: none)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-no-baseline", action="store_true",
