@@ -44,9 +44,13 @@ __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Pla
     const int tx = (int)threadIdx.x % BX, ty = (int)threadIdx.x / BX;
     const int i0 = i - ty, j0 = j - tx;
 
-    // step t for every fluid cell of the tile and its ring
+    // step t for every fluid cell of the tile and its ring: the interior
+    // nodes row by row (coalesced, pass 0), then the lattice's edge nodes
+    // column by column (pass 1), so that an edge column's cells share a few
+    // wavefronts and only those run the boundary code
+    for (int pass = 0; pass < 2; ++pass)
     for (int c = (int)threadIdx.x; c < NC; c += BX * BY) {
-        const int a = c / W, b = c - (c / W) * W;
+        const int a = pass == 0 ? c / W : c % H, b = pass == 0 ? c % W : c / H;
         int ci = i0 - 1 + a;
         const int cj = j0 - 1 + b;
         if ((unsigned)cj >= (unsigned)P.Nr) continue;
@@ -56,6 +60,7 @@ __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Pla
             if ((unsigned)ci >= (unsigned)P.Nz) continue;
         }
         const bool interior = interior_node(P, ci, cj);
+        if (interior != (pass == 0)) continue;
         float f[9], g[5], h[5], d[5];
         if (interior)
             gather_planes<S>(A, ((unsigned)ci * (unsigned)P.pitch + (unsigned)cj) *
