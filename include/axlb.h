@@ -65,7 +65,7 @@ extern "C" {
  * AA state (about 96 B per node in FP32) fits MI355X's 256 MB Infinity
  * Cache, AA is fastest; beyond it AB2 is, since HBM then carries every
  * byte and AB2 moves half as many per step (measured: 1024 x 2048 AA 37k
- * against AB2 30k MLUPS; 4096 x 4096 AA 27k against AB2 42k). */
+ * against AB2 33k MLUPS; 4096 x 4096 AA 27k against AB2 41k). */
 
 /* ---- time level of the central differences in the geometric sources ----
  * (eq. 4b, 4c, 7, 9; Section 3.2 only says "central difference").
