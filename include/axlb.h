@@ -65,7 +65,7 @@ extern "C" {
  * AA state (about 96 B per node in FP32) fits MI355X's 256 MB Infinity
  * Cache, AA is fastest; beyond it AB2 is, since HBM then carries every
  * byte and AB2 moves half as many per step (measured: 1024 x 2048 AA 37k
- * against AB2 33k MLUPS; 4096 x 4096 AA 27k against AB2 41k). */
+ * against AB2 35k MLUPS; 4096 x 4096 AA 27k against AB2 40k). */
 
 /* ---- time level of the central differences in the geometric sources ----
  * (eq. 4b, 4c, 7, 9; Section 3.2 only says "central difference").
@@ -216,7 +216,7 @@ int axlb_load(axlb_lattice *lat, const void *host, size_t bytes);
  * it); axlb_autotune times every shape for steps_per_trial steps on the
  * lattice itself, restores the state it found, selects the fastest, and
  * returns the per-step times in ms_per_step[AXLB_NTILES] (may be NULL).
- * The two-step launches of AXLB_LAYOUT_AB2 use a fixed 64 x 8 tile; the
+ * The two-step launches of AXLB_LAYOUT_AB2 use a fixed 32 x 8 tile; the
  * selected shape applies to its single steps. */
 #define AXLB_NTILES 8
 int axlb_tile_shape(int tile, int *tile_r, int *tile_z);

@@ -18,7 +18,7 @@
 
 namespace axlb {
 
-constexpr int TWO_BX = 64, TWO_BY = 8;
+constexpr int TWO_BX = 32, TWO_BY = 8;
 
 // The LDS tile of post-collision populations as a population source for
 // pull_all: node (i, j) sits in cell (i - i0 + 1, j - j0 + 1).
