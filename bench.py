@@ -241,8 +241,8 @@ def main():
                          "(reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; the path is single-GPU "
-              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        print("bench.py: the time step runs on one GPU; a slab decomposition across GPUs "
+              "is not implemented, so only --gpus 1 is measured", file=sys.stderr)
         sys.exit(2)
 
     import torch
