@@ -22,18 +22,33 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
-NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC = 0, 1, 2, 3, 4, 5
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, VELOCITY = 0, 1, 2, 3, 4, 5, 7
 DERIV_CURRENT, DERIV_PREVIOUS = 1, 2
 
 
+# Plain C11 in FP64; every operation rounded on its own (no contraction into
+# fused multiply-adds); OpenMP over the per-node loops.  The instruction set
+# is the portable x86-64-v3 level, since the library built here also runs on
+# other hosts; build_native() makes a copy for the host it runs on.
+CFLAGS = ["-std=c11", "-O3", "-march=x86-64-v3", "-ffp-contract=off", "-fopenmp", "-fPIC",
+          "-shared", "-Wall"]
+
+
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (plain C11, FP64, -O2)."""
+    """Compile ``liboracle.so`` with gcc."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc"] + CFLAGS + ["-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def build_native(path: str) -> str:
+    """Compile a copy of the oracle tuned for this host's CPU (-march=native)
+    at ``path``; the arithmetic is the same as build()'s."""
+    flags = [f if not f.startswith("-march=") else "-march=native" for f in CFLAGS]
+    subprocess.check_call(["gcc"] + flags + ["-o", path, _SRC, "-lm"])
+    return path
 
 
 class _BC(C.Structure):
@@ -54,12 +69,14 @@ _lib = None
 _dp = C.POINTER(C.c_double)
 
 
-def _load():
+def _load(path: str | None = None):
+    """The oracle library (``path``: another build of the same source, such
+    as build_native()'s, loaded instead of the in-tree one)."""
     global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+    if _lib is None or path is not None:
+        if path is None and not os.path.exists(_LIB):
             build(force=False)
-        lib = C.CDLL(_LIB)
+        lib = C.CDLL(path or _LIB)
         lib.orc_create.restype = C.c_void_p
         lib.orc_create.argtypes = [C.POINTER(_Params)] + [_dp] * 5
         lib.orc_destroy.argtypes = [C.c_void_p]
@@ -78,8 +95,24 @@ def _load():
         lib.orc_equilibrium_adv.argtypes = [C.c_double] * 3 + [_dp]
         lib.orc_collide_f.argtypes = [_dp] + [C.c_double] * 6 + [_dp, _dp]
         lib.orc_collide_adv.argtypes = [_dp] + [C.c_double] * 4 + [_dp, _dp]
+        lib.orc_half_step.argtypes = [C.POINTER(_Params), C.c_double, _dp, _dp, _dp]
+        lib.orc_residual.argtypes = [C.c_long] + [_dp] * 8 + [C.c_long]
+        lib.orc_residual.restype = C.c_double
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_threads.restype = C.c_int
+        if path is not None:
+            return lib
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's per-node loops (results do not depend on it)."""
+    _load().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(_load().orc_threads())
 
 
 def _ptr(a):
@@ -124,6 +157,51 @@ def collide_adv(g, s, ux, uy, S, om):
     return out
 
 
+def params(case: dict, deriv_mode: int = DERIV_PREVIOUS) -> _Params:
+    """The oracle's parameter block for a case dict as produced by
+    ``paper_1806_10241_amd.inputs``."""
+    p = _Params()
+    p.Nr, p.Nz = case["Nr"], case["Nz"]
+    p.cylinder = int(case.get("cylinder", 0))
+    p.r_inner = float(case.get("r_inner", 0.0))
+    p.nu, p.alpha = float(case["nu"]), float(case["alpha"])
+    p.omega3 = float(case.get("omega3", 1.0))
+    for k in ("omega6", "omega7", "omega8", "omega_psi3", "omega_psi4",
+              "omega_phi3", "omega_phi4"):
+        setattr(p, k, float(case.get(k, 1.0)))
+    p.g_axial = float(case.get("g_axial", 0.0))
+    # Rayleigh number with L = Nr (gap or cylinder radius) and dT = 1
+    # (Section 3.2): g beta = Ra nu alpha / L^3.
+    p.gbeta = float(case.get("Ra", 0.0)) * p.nu * p.alpha / float(p.Nr) ** 3
+    p.T0 = float(case.get("T0", 0.0))
+    p.deriv_mode = int(deriv_mode)
+    for (face, fld), (kind, value) in case["bc"].items():
+        p.bc[face][fld].kind = int(kind)
+        p.bc[face][fld].value = float(value)
+    return p
+
+
+def half_step(case: dict, y: float, mom, d) -> dict:
+    """The oracle's pre-collision half step of one node at radius y with
+    output moments mom = (rho, j_x, j_y, psi, phi) and central differences
+    d = (d_x u_y, d_y u_x, d_y u_y, d_y u_theta, d_y phi)."""
+    p = params(case)
+    mom = _f64(mom, 5)
+    d = _f64(d, 5)
+    out = np.zeros(10)
+    _load().orc_half_step(C.byref(p), float(y), _ptr(mom), _ptr(d), _ptr(out))
+    keys = ("MA", "Fx", "Fy", "Spsi", "Sphi", "rho", "ux", "uy", "psi", "phi")
+    return dict(zip(keys, out.tolist()))
+
+
+def residual(now: dict, then: dict, K: int) -> float:
+    """The oracle's convergence residual between field snapshots ``now`` and
+    ``then`` (dicts with ur, uz, uth, T) taken K steps apart."""
+    a = [_f64(now[k]) for k in ("ur", "uz", "uth", "T")]
+    b = [_f64(then[k], a[0].size) for k in ("ur", "uz", "uth", "T")]
+    return float(_load().orc_residual(a[0].size, *[_ptr(x) for x in a + b], int(K)))
+
+
 # ---------------------------------------------------------------- lattice
 class Lattice:
     """One oracle lattice.  ``case`` is a dict as produced by
@@ -131,26 +209,10 @@ class Lattice:
     alpha, omega3, ..., g_axial, gbeta, T0, bc); ``deriv_mode`` selects the
     time level of the fields inside the central differences."""
 
-    def __init__(self, case: dict, deriv_mode: int = DERIV_PREVIOUS, fields: dict | None = None):
-        lib = _load()
-        p = _Params()
-        p.Nr, p.Nz = case["Nr"], case["Nz"]
-        p.cylinder = int(case.get("cylinder", 0))
-        p.r_inner = float(case.get("r_inner", 0.0))
-        p.nu, p.alpha = float(case["nu"]), float(case["alpha"])
-        p.omega3 = float(case.get("omega3", 1.0))
-        for k in ("omega6", "omega7", "omega8", "omega_psi3", "omega_psi4",
-                  "omega_phi3", "omega_phi4"):
-            setattr(p, k, float(case.get(k, 1.0)))
-        p.g_axial = float(case.get("g_axial", 0.0))
-        # Rayleigh number with L = Nr (gap or cylinder radius) and dT = 1
-        # (Section 3.2): g beta = Ra nu alpha / L^3.
-        p.gbeta = float(case.get("Ra", 0.0)) * p.nu * p.alpha / float(p.Nr) ** 3
-        p.T0 = float(case.get("T0", 0.0))
-        p.deriv_mode = int(deriv_mode)
-        for (face, fld), (kind, value) in case["bc"].items():
-            p.bc[face][fld].kind = int(kind)
-            p.bc[face][fld].value = float(value)
+    def __init__(self, case: dict, deriv_mode: int = DERIV_PREVIOUS, fields: dict | None = None,
+                 lib=None):
+        lib = lib or _load()
+        p = params(case, deriv_mode)
         self.Nr, self.Nz = p.Nr, p.Nz
         self.N = p.Nr * p.Nz
         fields = fields or {}

@@ -16,6 +16,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Section 2.2, eq. (10): D2Q9 particle velocities in the order of the paper. */
 static const int EX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -67,7 +70,16 @@ static int reflect_y(const int *ex, const int *ey, int nq, int q)
 static int is_wall(int kind)
 {
     return kind == ORC_NOSLIP || kind == ORC_DIRICHLET || kind == ORC_OMEGA_R ||
-           kind == ORC_ADIABATIC;
+           kind == ORC_ADIABATIC || kind == ORC_VELOCITY;
+}
+
+/* Velocity normal to a face that imposes one (VELOCITY for f), as the
+ * component along +y (radial faces) or +x (axial faces); 0 for walls at
+ * rest. */
+static double normal_velocity(const orc_params *p, int face)
+{
+    const orc_bc *bc = &p->bc[face][ORC_FLOW];
+    return bc->kind == ORC_VELOCITY ? bc->value : 0.0;
 }
 
 /* Radial coordinate of node row j: nodes sit half a spacing off the wall
@@ -235,11 +247,18 @@ static double wall_scalar(const orc_bc *bc, double ym)
 /* Post-stream population q of distribution fld at node (i, j): the pull
  * form of eq. (16b), (33b), (46b).  Where the source node x - e_q is not a
  * fluid node, the boundary rules apply, in this precedence per link:
- *   1. a solid wall (radial faces first, then axial faces):
- *      f: half-way bounce-back (no-slip, Section 3.2);
+ *   1. a wall (radial faces first, then axial faces):
+ *      f: half-way bounce-back (no-slip, Section 3.2).  Reading for a wall
+ *      that imposes a normal velocity u_w (an inlet or outlet, which the
+ *      paper's cases do not use): the moving-wall form of bounce-back,
+ *      post[opp] + 2 w_q rho_0 (e_q . u_w) / c_s^2 with rho_0 = 1, which
+ *      carries the mass flux rho_0 u_w through the wall;
  *      g, h: Reading of the cited advection-diffusion wall scheme: half-way
- *      anti-bounce-back for an imposed value, -post[opp] + 2 w s_w with the
- *      D2Q5 weight w = 1/6, and bounce-back for zero flux (ADIABATIC);
+ *      anti-bounce-back for an imposed value, -post[opp] + 2 g^eq+_q(s_w,
+ *      u_w), twice the even part of the D2Q5 equilibrium at the wall value,
+ *      s_w (c_s^2 + u_n^2) for the one link that crosses the wall (u_n the
+ *      normal velocity, 0 at a wall at rest, where this is 2 w s_w with
+ *      w = 1/6), and bounce-back for zero flux (ADIABATIC);
  *   2. the symmetry axis (Section 3.3, "mirror"): specular reflection, the
  *      population comes from the node shifted by e_x along the axis with
  *      its radial velocity reversed; g is odd there (u_theta = 0 on the
@@ -264,9 +283,15 @@ static double pulled(const orc_state *s, int fld, int q, int i, int j)
     if (wall >= 0) {
         const orc_bc *bc = &p->bc[wall][fld];
         const double own = post[node(s, i, j) * nq + opposite(ex, ey, nq, q)];
-        if (fld == ORC_FLOW || bc->kind == ORC_ADIABATIC) return own;
+        const double un = normal_velocity(p, wall);
+        if (fld == ORC_FLOW) {
+            const double w = phi1d(ex[q], 0.0) * phi1d(ey[q], 0.0); /* lattice weight */
+            const double eu = wall <= ORC_R_OUT ? ey[q] * un : ex[q] * un;
+            return own + 2.0 * w * eu / CS2;
+        }
+        if (bc->kind == ORC_ADIABATIC) return own;
         const double ym = y_of(s, j) - 0.5 * ey[q];
-        return -own + 2.0 * (1.0 / 6.0) * wall_scalar(bc, ym);
+        return -own + (CS2 + un * un) * wall_scalar(bc, ym);
     }
     if (fy == ORC_R_IN && p->bc[ORC_R_IN][fld].kind == ORC_MIRROR) {
         qs = reflect_y(ex, ey, nq, q);
@@ -283,8 +308,9 @@ static double pulled(const orc_state *s, int fld, int q, int i, int j)
  * the fluid the value comes from a ghost point mirrored through the wall,
  * q_g = 2 q_w - q_1 (q_1 = value at the boundary node), i.e. -q_1 for the
  * meridian velocities at a no-slip wall, 2 q_w - q_1 for an imposed u_theta
- * or T, q_1 for zero flux; at the axis even variables (u_x, T) take q_1 and
- * odd ones (u_y, u_theta) take -q_1; a periodic face wraps. */
+ * or T, q_1 for zero flux, and 2 u_w - q_1 for the normal velocity at a wall
+ * that imposes one; at the axis even variables (u_x, T) take q_1 and odd
+ * ones (u_y, u_theta) take -q_1; a periodic face wraps. */
 static double neighbour(const orc_state *s, const double *F, int v, int i, int j,
                         int di, int dj)
 {
@@ -303,7 +329,10 @@ static double neighbour(const orc_state *s, const double *F, int v, int i, int j
     if (bc->kind == ORC_PERIODIC) return F[node(s, (ni + p->Nz) % p->Nz, nj) * 4 + v];
     if (bc->kind == ORC_MIRROR) return (v == VX || v == VP) ? q1 : -q1;
     if (bc->kind == ORC_ADIABATIC) return q1;
-    if (v == VX || v == VY) return -q1;
+    if (v == VX || v == VY) {
+        const int normal = face <= ORC_R_OUT ? VY : VX;
+        return v == normal ? 2.0 * normal_velocity(p, face) - q1 : -q1;
+    }
     const double yw = y_of(s, j) + 0.5 * dj; /* wall radius, or y_j on an axial face */
     return 2.0 * wall_scalar(bc, yw) - q1;
 }
@@ -317,6 +346,8 @@ static void stream_and_moments(const orc_state *s, double *fs, double *gs, doubl
                                double *mom, double *cur)
 {
     const int Nr = s->p.Nr, Nz = s->p.Nz;
+    /* every node writes only its own entries: rows may run on any thread */
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nr; ++j) {
             const int n = node(s, i, j);
@@ -380,20 +411,11 @@ static void sources_at(const orc_params *p, double y, double rho, double Jx, dou
  * stops when the update is at round-off, and the returned state is then
  * re-formed from the sources evaluated at it, so that eq. (21), (38), (48)
  * hold with exactly the sources that the collision receives. */
-static void sources_half_step(const orc_state *s, int i, int j, const double *mom,
-                              const double *D, half_step *o)
+static void half_step_solve(const orc_params *p, double y, const double m[5], const double d[5],
+                            half_step *o)
 {
-    const orc_params *p = &s->p;
-    const double *m = mom + node(s, i, j) * 5;
     const double ro = m[0], jxo = m[1], jyo = m[2], pso = m[3], pho = m[4];
-    const double y = y_of(s, j), nu = p->nu;
-
-    double d[5];
-    d[0] = 0.5 * (neighbour(s, D, VY, i, j, +1, 0) - neighbour(s, D, VY, i, j, -1, 0));
-    d[1] = 0.5 * (neighbour(s, D, VX, i, j, 0, +1) - neighbour(s, D, VX, i, j, 0, -1));
-    d[2] = 0.5 * (neighbour(s, D, VY, i, j, 0, +1) - neighbour(s, D, VY, i, j, 0, -1));
-    d[3] = 0.5 * (neighbour(s, D, VT, i, j, 0, +1) - neighbour(s, D, VT, i, j, 0, -1));
-    d[4] = 0.5 * (neighbour(s, D, VP, i, j, 0, +1) - neighbour(s, D, VP, i, j, 0, -1));
+    const double nu = p->nu;
 
     double rho = ro, Jy = jyo, psi = pso;
     for (int it = 0; it < 200; ++it) {
@@ -418,6 +440,29 @@ static void sources_half_step(const orc_state *s, int i, int j, const double *mo
     o->uy = (jyo + 0.5 * o->Fy) / o->rho;
     o->psi = pso + 0.5 * o->Spsi;
     o->phi = pho + 0.5 * o->Sphi;
+}
+
+/* The half step of node (i, j): its output moments and the central
+ * differences (Section 3.2) of the fields in D. */
+static void sources_half_step(const orc_state *s, int i, int j, const double *mom,
+                              const double *D, half_step *o)
+{
+    double d[5];
+    d[0] = 0.5 * (neighbour(s, D, VY, i, j, +1, 0) - neighbour(s, D, VY, i, j, -1, 0));
+    d[1] = 0.5 * (neighbour(s, D, VX, i, j, 0, +1) - neighbour(s, D, VX, i, j, 0, -1));
+    d[2] = 0.5 * (neighbour(s, D, VY, i, j, 0, +1) - neighbour(s, D, VY, i, j, 0, -1));
+    d[3] = 0.5 * (neighbour(s, D, VT, i, j, 0, +1) - neighbour(s, D, VT, i, j, 0, -1));
+    d[4] = 0.5 * (neighbour(s, D, VP, i, j, 0, +1) - neighbour(s, D, VP, i, j, 0, -1));
+    half_step_solve(&s->p, y_of(s, j), mom + node(s, i, j) * 5, d, o);
+}
+
+void orc_half_step(const orc_params *p, double y, const double mom[5], const double d[5],
+                   double out[10])
+{
+    half_step o;
+    half_step_solve(p, y, mom, d, &o);
+    out[0] = o.MA; out[1] = o.Fx; out[2] = o.Fy; out[3] = o.Spsi; out[4] = o.Sphi;
+    out[5] = o.rho; out[6] = o.ux; out[7] = o.uy; out[8] = o.psi; out[9] = o.phi;
 }
 
 static void omegas(const orc_params *p, double om9[9], double omg[5], double omh[5])
@@ -451,7 +496,8 @@ void orc_step(orc_state *s, long n)
         const double *D = s->p.deriv_mode == ORC_DERIV_CURRENT ? cur : s->lag;
         /* pass 2: M^1/2 F^1/2 C F^1/2 M^1/2 (eq. 20) and R^1/2 C R^1/2
          * (eq. 37, 45), written as pre-half step + collision with the full
-         * source moment (eq. 23, 40) */
+         * source moment (eq. 23, 40); nodes are independent */
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < Nz; ++i)
             for (int j = 0; j < Nr; ++j) {
                 const int k = node(s, i, j);
@@ -486,6 +532,7 @@ void orc_fields(const orc_state *s, double *rho, double *ur, double *uz, double 
     double *cur = malloc(sizeof(double) * 4 * N);
     stream_and_moments(s, fs, gs, hs, mom, cur);
     const double *D = s->p.deriv_mode == ORC_DERIV_CURRENT ? cur : s->lag;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < Nz; ++i)
         for (int j = 0; j < Nr; ++j) {
             const int k = node(s, i, j);
@@ -569,14 +616,20 @@ static int valid(const orc_params *p)
         for (int face = 0; face < 4; ++face) {
             const int k = p->bc[face][fld].kind;
             if (face >= ORC_Z_LO && k == ORC_MIRROR) return 0;
-            if (fld == ORC_FLOW && is_wall(k) && k != ORC_NOSLIP) return 0;
+            if (fld == ORC_FLOW && is_wall(k) && k != ORC_NOSLIP && k != ORC_VELOCITY) return 0;
+            if (fld != ORC_FLOW && k == ORC_VELOCITY) return 0;
             if (fld == ORC_THERMAL && (k == ORC_NOSLIP || k == ORC_OMEGA_R)) return 0;
         }
     }
-    /* a face is a wall for all three distributions or for none */
+    /* a face is a wall for all three distributions or for none; where fluid
+     * crosses it (VELOCITY), g and h carry imposed values */
     for (int face = 0; face < 4; ++face) {
         const int w = is_wall(p->bc[face][0].kind);
         if (is_wall(p->bc[face][1].kind) != w || is_wall(p->bc[face][2].kind) != w) return 0;
+        if (p->bc[face][0].kind == ORC_VELOCITY &&
+            (p->bc[face][1].kind == ORC_ADIABATIC || p->bc[face][2].kind != ORC_DIRICHLET ||
+             !isfinite(p->bc[face][0].value)))
+            return 0;
     }
     return 1;
 }
@@ -655,4 +708,54 @@ void orc_get_populations(const orc_state *s, double *f9, double *g5, double *h5)
             if (h5) h5[a * N + k] = s->h[5 * k + a];
         }
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Convergence residual.  Reading: the paper runs its cases "to steady state"
+ * without defining the test, so the residual is the largest relative change
+ * per step between two snapshots K steps apart,
+ *   max over c in {u_r, u_z, u_theta} of ||c_now - c_then|| / (K ||speed_now||)
+ *   and ||T_now - T_then|| / (K ||T_now||),
+ * with ||.|| the Euclidean norm over the nodes and speed = |(u_r, u_z,
+ * u_theta)|.  The velocity components share the speed norm because one of
+ * them can be pure round-off (u_r of a parallel flow).  A term whose norm is
+ * zero is skipped; K <= 0 gives +inf. */
+double orc_residual(long n, const double *ur1, const double *uz1, const double *uth1,
+                    const double *T1, const double *ur0, const double *uz0,
+                    const double *uth0, const double *T0, long K)
+{
+    if (K <= 0) return INFINITY;
+    const double *now[3] = {ur1, uz1, uth1}, *then[3] = {ur0, uz0, uth0};
+    double speed2 = 0.0, d2[3] = {0.0, 0.0, 0.0}, t2 = 0.0, dt2 = 0.0;
+    for (long k = 0; k < n; ++k) {
+        for (int c = 0; c < 3; ++c) {
+            speed2 += now[c][k] * now[c][k];
+            d2[c] += (now[c][k] - then[c][k]) * (now[c][k] - then[c][k]);
+        }
+        t2 += T1[k] * T1[k];
+        dt2 += (T1[k] - T0[k]) * (T1[k] - T0[k]);
+    }
+    double r = 0.0;
+    if (speed2 > 0.0)
+        for (int c = 0; c < 3; ++c) r = fmax(r, sqrt(d2[c]) / ((double)K * sqrt(speed2)));
+    if (t2 > 0.0) r = fmax(r, sqrt(dt2) / ((double)K * sqrt(t2)));
+    return r;
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -27,11 +27,15 @@ enum { ORC_R_IN = 0, ORC_R_OUT = 1, ORC_Z_LO = 2, ORC_Z_HI = 3 };
 /* The three distribution functions: f (D2Q9), g (D2Q5, psi), h (D2Q5, T). */
 enum { ORC_FLOW = 0, ORC_SWIRL = 1, ORC_THERMAL = 2 };
 /* Boundary kinds.  NOSLIP, DIRICHLET, OMEGA_R and ADIABATIC are solid walls
- * (half-way between the last fluid node and the first solid node); MIRROR is
- * the symmetry axis; PERIODIC wraps the axial direction. */
+ * (half-way between the last fluid node and the first solid node); VELOCITY
+ * (f only) is a wall of the same kind through which the fluid crosses with
+ * the imposed normal velocity `value` (along +y on radial faces, +x on axial
+ * faces: an inlet or outlet), with g and h imposed there; MIRROR is the
+ * symmetry axis; PERIODIC wraps the axial direction.  (6 is left unused so
+ * that the numbering matches the HIP library's.) */
 enum {
     ORC_NOSLIP = 0, ORC_PERIODIC = 1, ORC_MIRROR = 2,
-    ORC_DIRICHLET = 3, ORC_OMEGA_R = 4, ORC_ADIABATIC = 5
+    ORC_DIRICHLET = 3, ORC_OMEGA_R = 4, ORC_ADIABATIC = 5, ORC_VELOCITY = 7
 };
 /* Fields inside the central differences of the sources:
  * 1 = output fields of the current step (after streaming, eq. 18, 35, 47),
@@ -102,6 +106,25 @@ void orc_collide_f(const double f[9], double rho, double ux, double uy,
  * implementation, eq. (41)/(51), and g + L q (eq. 33a/46a).  om[1..4]. */
 void orc_collide_adv(const double g[5], double s, double ux, double uy,
                      double S, const double om[5], double gp[5]);
+
+/* Pre-collision half source step of one node at radius y (eq. 21, 38, 48
+ * with the sources of eq. 4, 5, 7, 9 evaluated at the half-step state):
+ * mom = {rho^o, j_x^o, j_y^o, psi^o, phi^o}, d = {d_x u_y, d_y u_x, d_y u_y,
+ * d_y u_theta, d_y phi}; out = {M^A, F_x, F_y, S_psi, S_phi, rho, u_x, u_y,
+ * psi, phi}. */
+void orc_half_step(const orc_params *p, double y, const double mom[5], const double d[5],
+                   double out[10]);
+
+/* Convergence residual between two snapshots of n nodes taken K steps
+ * apart (the definition is at the function). */
+double orc_residual(long n, const double *ur1, const double *uz1, const double *uth1,
+                    const double *T1, const double *ur0, const double *uz0,
+                    const double *uth0, const double *T0, long K);
+
+/* Threads of the per-node loops (OpenMP build); results do not depend on
+ * the count, since every node is computed on its own. */
+void orc_set_threads(int n);
+int orc_threads(void);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,7 @@ import numpy as np
 # Faces, distributions and boundary kinds (numbering of the C interface).
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
-NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC = 0, 1, 2, 3, 4, 5
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, VELOCITY = 0, 1, 2, 3, 4, 5, 7
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -124,6 +124,30 @@ def couette_poiseuille_conduction(Nr: int = 30, Nz: int = 8, r_inner: float = 10
                 r_inner=float(r_inner), nu=nu, alpha=alpha, Pr=nu / alpha, Ra=0.0,
                 g_axial=g, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5,
                 fields=lambda: {"T": np.full((Nz, Nr), 0.5)})
+
+
+def porous_annulus(Nr: int = 30, Nz: int = 4, r_inner: float = 10.0, Q: float = 0.1,
+                   u_inner: float = 1e-3, u_outer: float = 0.0, g: float = 1e-6,
+                   nu: float = 0.1, alpha: float = 0.1) -> dict:
+    """Radial throughflow between porous coaxial cylinders, periodic along z:
+    fluid enters through the inner wall with u_r = Q/R_i and leaves through
+    the outer wall with u_r = Q/R_o (imposed-velocity walls), the inner wall
+    turns (u_theta = u_inner) and is hot (T = 1), the outer wall turns with
+    u_outer and is cold (T = 0), and an axial body force g drives axial flow.
+    No buoyancy.  Nr counts fluid rows; the walls sit at r_inner and
+    r_inner + Nr."""
+    Ri, Ro = float(r_inner), float(r_inner) + Nr
+    bc = {}
+    bc[(R_IN, FLOW)] = (VELOCITY, Q / Ri)
+    bc[(R_IN, SWIRL)] = (DIRICHLET, u_inner)
+    bc[(R_IN, THERMAL)] = (DIRICHLET, 1.0)
+    bc[(R_OUT, FLOW)] = (VELOCITY, Q / Ro)
+    bc[(R_OUT, SWIRL)] = (DIRICHLET, u_outer)
+    bc[(R_OUT, THERMAL)] = (DIRICHLET, 0.0)
+    _periodic_z(bc)
+    return dict(name="porous_annulus", Nr=Nr, Nz=Nz, cylinder=0, r_inner=Ri, nu=nu,
+                alpha=alpha, Pr=nu / alpha, Ra=0.0, g_axial=g, T0=0.5, omega3=1.0, bc=bc,
+                T_ref=0.5, Q=Q, fields=lambda: {"T": np.full((Nz, Nr), 0.5)})
 
 
 def annulus_convection(Nr: int = 256, Nz: int = 256, radius_ratio: float = 2.0,
