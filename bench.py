@@ -2,12 +2,15 @@
 
 Workload: the 1024 x 2048 rotating-lid cylinder with buoyancy (Re = 1000,
 Ri = 0.5, Pr = 1), FP32 arithmetic and storage, single-buffer (AA) layout,
-100-step HIP graph bundles.  A step is one update of every node's 19
-populations (D2Q9 + 2 x D2Q5).  Prints one JSON line.
+steps replayed as captured HIP graphs.  A step is one update of every node's
+19 populations (D2Q9 + 2 x D2Q5).  Prints one JSON line.
 
 The dominant (only) kernel per step is the fused step kernel; its
 algorithmic traffic is 152 B per node update (19 populations x 4 B, read and
-written once), so achieved GB/s = 152 * nodes / average step time.
+written once), so achieved GB/s = 152 * nodes / average step time.  Beside
+the headline the line carries: the same step on a lattice too large for the
+Infinity Cache, the error of every storage type against the FP64 oracle,
+the batched and served workloads, and the oracle's own speed on the host.
 """
 from __future__ import annotations
 
@@ -74,18 +77,114 @@ def measured_traffic(storage: str, Nr: int, Nz: int):
         return None
 
 
-def cpu_baseline(case, steps: int):
-    """The FP64 oracle, single-threaded, on the first `steps` steps of the
-    same workload; MLUPS over the stepping only."""
+def step_working_set(Nr: int, Nz: int, storage: str, layout: str) -> int:
+    """Bytes a step touches: the population buffer(s) and both time levels of
+    the lagged fields (FP32 velocities with FP32 storage, binary16 with
+    16-bit storage; T in FP32), rows padded to 64 nodes."""
+    plane = Nz * ((Nr + 63) // 64 * 64)
+    es = 4 if storage == "f32" else 2
+    pops = 19 * es * plane * (1 if layout == "aa" else 2)
+    return pops + 2 * (3 * es + 4) * plane
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Threads this process may use: the OpenMP setting if there is one,
+    else the CPUs in its affinity mask."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+ACCURACY_CASE = dict(Nr=128, Nz=256, Re=1000.0, Ri=0.5, u_noise=1e-4)
+ACCURACY_STEPS = 1000
+
+
+def accuracy_runs():
+    """The benchmark's physics at reduced resolution (rotating-lid cylinder
+    128 x 256, same Re, Ri, Pr and seeded noise) after 1000 steps with each
+    storage type on the GPU: fields and wall Nusselt numbers."""
+    from paper_1806_10241_amd import axlb
+    from paper_1806_10241_amd import inputs as I
+    c = I.rotating_lid_cylinder(**ACCURACY_CASE)
+    out = {}
+    for st in ("f32", "f16", "bf16"):
+        lat = axlb.Lattice(c, storage=st)
+        lat.step(ACCURACY_STEPS)
+        out[st] = (lat.fields(), lat.nusselt())
+        lat.close()
+    return out
+
+
+def rel_errors(F, R):
+    """Relative L2 errors after the parity tests' convention: rho - 1 and T
+    against their own norms, velocity components against the speed norm;
+    plus the largest Nusselt error."""
+    speed = np.linalg.norm(np.sqrt(R["ur"] ** 2 + R["uz"] ** 2 + R["uth"] ** 2))
+    e = {}
+    for k in ("ur", "uz", "uth"):
+        e[k] = float(np.linalg.norm(F[k] - R[k]) / speed)
+    e["T"] = float(np.linalg.norm(F["T"] - R["T"]) / np.linalg.norm(R["T"]))
+    e["rho-1"] = float(np.linalg.norm(F["rho"] - R["rho"]) / np.linalg.norm(R["rho"] - 1.0))
+    return e
+
+
+def cpu_leg(case, single_steps: int, multi_steps: int, gpu_accuracy):
+    """The FP64 oracle on this host: built for this CPU (-march=native), timed
+    on the first steps of the benchmark workload with one thread and with
+    every core this process may use; and, as the reference of the accuracy
+    report, run on the reduced-resolution case that accuracy_runs() ran."""
+    import tempfile
+
     import oracle
-    L = oracle.Lattice(case, deriv_mode=oracle.DERIV_PREVIOUS, fields=case["fields"]())
-    t0 = time.perf_counter()
-    L.step(steps)
-    dt = time.perf_counter() - t0
-    mlups = case["Nr"] * case["Nz"] * steps / dt / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "%d steps of the %dx%d workload, FP64, one thread (%.1f s)"
-                      % (steps, case["Nr"], case["Nz"], dt)}
+    from paper_1806_10241_amd import inputs as I
+    with tempfile.TemporaryDirectory() as d:
+        lib = oracle._load(oracle.build_native(os.path.join(d, "liboracle_native.so")))
+        cores = host_cores()
+        timings = []
+        for threads, steps in ((1, single_steps), (cores, multi_steps)):
+            lib.orc_set_threads(threads)
+            L = oracle.Lattice(case, deriv_mode=oracle.DERIV_PREVIOUS, fields=case["fields"](),
+                               lib=lib)
+            t0 = time.perf_counter()
+            L.step(steps)
+            dt = time.perf_counter() - t0
+            timings.append((case["Nr"] * case["Nz"] * steps / dt / 1e6, steps, dt))
+            del L
+        accuracy = None
+        if gpu_accuracy is not None:
+            c = I.rotating_lid_cylinder(**ACCURACY_CASE)
+            R = oracle.Lattice(c, deriv_mode=oracle.DERIV_PREVIOUS, fields=c["fields"](), lib=lib)
+            R.step(ACCURACY_STEPS)
+            Rf, Rnu = R.fields(), R.nusselt()
+            del R
+            accuracy = {"case": "rotating-lid cylinder %dx%d, Re=%g, Ri=%g, %d steps"
+                                % (c["Nr"], c["Nz"], c["Re"], c["Ri"], ACCURACY_STEPS),
+                        "bars": {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-3, "nusselt": 5e-3}}
+            for st, (F, nu) in gpu_accuracy.items():
+                e = rel_errors(F, Rf)
+                e["nusselt"] = float(max(abs(a - b) / abs(b) for a, b in zip(nu, Rnu)))
+                accuracy[st] = {k: float("%.3g" % v) for k, v in e.items()}
+    (v1, s1, dt1), (vn, sn, dtn) = timings
+    base = {"value": round(vn, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%d steps of the %dx%d workload, FP64, %d threads (%.1f s); "
+                      "built -O3 -march=native on %s" % (sn, case["Nr"], case["Nz"], cores, dtn,
+                                                         cpu_model()),
+            "single_thread": {"value": round(v1, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": "%d steps (%.1f s)" % (s1, dt1)},
+            "cpu_model": cpu_model()}
+    return base, accuracy
 
 
 def bench_batched(n, steps, warmup, baseline_steps):
@@ -168,7 +267,8 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, 
     _, node_updates = pool.usage()
     lat_s = np.array([done[r] - arrival[r] for r in arrival])
     pool.close()
-    out = {"requests": n, "rate_per_s": rate, "tol": tol, "max_steps": max_steps,
+    out = {"requests": n, "rate_per_s": rate, "arrival_span_s": round(trace[-1][0], 3),
+           "tol": tol, "max_steps": max_steps,
            "budget_gib": budget_gib, "admission": order, "node_window": window,
            "grid": "Nr 64..%d x Nz 64..%d" % (2 ** max_nr_log2, 2 ** max_nz_log2),
            "p50_s": round(float(np.percentile(lat_s, 50)), 4),
@@ -199,6 +299,110 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, 
     return out
 
 
+def headline(args, case, stream):
+    """The timed run: warmup, then exactly args.steps steps replayed as
+    graphs captured beforehand, bracketed by HIP events on the lattice's
+    stream."""
+    import torch
+
+    from paper_1806_10241_amd import axlb
+    nodes = case["Nr"] * case["Nz"]
+    lat = axlb.Lattice(case, storage=args.storage, layout=args.layout, stream=stream,
+                       deriv=args.deriv)
+    print("bench: %dx%d %s %s, warmup %d" % (args.Nr, args.Nz, args.storage, args.layout,
+                                             args.warmup), file=sys.stderr, flush=True)
+    if args.tile >= 0:
+        lat.set_tile(args.tile)
+        tune = None
+    else:
+        best, ms = lat.autotune(steps_per_trial=40)
+        tune = {"%dx%d" % axlb.tile_shape(t): round(m * 1e3, 2) for t, m in enumerate(ms)}
+        print("bench: autotune us/step per tile %s" % tune, file=sys.stderr, flush=True)
+    _, tile_rz = lat.tile()
+    lat.step(args.warmup)
+    if not args.single_launches:
+        lat.prepare_steps(args.steps)
+    lat.sync()
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    if args.single_launches:
+        for _ in range(args.steps):
+            lat.step(1)
+    else:
+        lat.step(args.steps)
+    end.record(stream)
+    end.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end)
+    r = lat.residual()
+    lat.close()
+    ms_per_step = ms / args.steps
+    if args.single_launches:
+        launch = "one kernel launch per step"
+    else:
+        bundles, tail = divmod(args.steps, 100)
+        parts = (["%d replays of a 100-step graph" % bundles] if bundles else []) + \
+            (["one %d-step graph" % tail] if tail >= 2 else []) + \
+            (["one single launch"] if tail == 1 else [])
+        launch = ", then ".join(parts) + " (captured before the timed region)"
+    print("bench: timed %d steps in %.3f s (events %.4f ms/step)" % (args.steps, wall, ms_per_step),
+          file=sys.stderr, flush=True)
+    return {"ms_per_step": ms_per_step, "mlups": nodes * args.steps / (ms / 1e3) / 1e6,
+            "launch": launch, "tile": "%dx%d" % tile_rz, "autotune_us_per_step": tune,
+            "finite": bool(r == r)}
+
+
+def out_of_cache(Nr, Nz, steps, storage="f32"):
+    """The same workload on a lattice whose state exceeds the 256 MB Infinity
+    Cache (so HBM carries every byte), single-buffer (AA) and two steps per
+    launch on two buffers (AB2); graph replays, HIP events."""
+    import torch
+
+    from paper_1806_10241_amd import axlb
+    from paper_1806_10241_amd import inputs as I
+    case = I.rotating_lid_cylinder(Nr=Nr, Nz=Nz, Re=1000.0, Ri=0.5, u_noise=1e-4)
+    nodes = Nr * Nz
+    out = {"Nr": Nr, "Nz": Nz, "storage": storage, "steps": steps}
+    for layout in ("aa", "ab2"):
+        stream = torch.cuda.Stream()
+        lat = axlb.Lattice(case, storage=storage, layout=layout, stream=stream)
+        if layout == "aa":
+            lat.set_tile(axlb_default_tile())
+        lat.step(20)
+        lat.prepare_steps(steps)
+        lat.sync()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lat.step(steps)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / steps
+        state = step_working_set(Nr, Nz, storage, layout)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        achieved = BYTES_PER_UPDATE[storage] * nodes / (ms / 1e3) / 1e9
+        out[layout] = {"mlups": round(nodes / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 4),
+                       "working_set_bytes": state, "achieved_gbs": round(achieved, 1),
+                       "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    return out
+
+
+def axlb_default_tile():
+    """The 256 x 1 tile (the autotuner's usual choice at these widths)."""
+    from paper_1806_10241_amd import axlb
+    for t in range(axlb.NTILES):
+        if axlb.tile_shape(t) == (256, 1):
+            return t
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,18 +414,25 @@ def main():
                     help="time level of the source-term derivatives (current needs --layout ab)")
     ap.add_argument("--Nr", type=int, default=1024)
     ap.add_argument("--Nz", type=int, default=2048)
-    ap.add_argument("--cpu-steps", type=int, default=30,
-                    help="steps of the oracle on the benchmark lattice (~15 s on one core)")
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="steps of the oracle on one thread on the benchmark lattice")
+    ap.add_argument("--cpu-steps-all", type=int, default=100,
+                    help="steps of the oracle on every core on the benchmark lattice")
     ap.add_argument("--u-noise", type=float, default=1e-4,
                     help="seeded velocity noise of the initial state (0: at rest, so that "
                          "the swirl populations stay exactly zero away from the lid)")
     ap.add_argument("--tile", type=int, default=-1,
                     help="step-kernel tile shape; -1: autotune on the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--ooc-Nr", type=int, default=2048,
+                    help="width of the out-of-cache lattice (0: skip that measurement)")
+    ap.add_argument("--ooc-Nz", type=int, default=4096)
+    ap.add_argument("--ooc-steps", type=int, default=200)
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10000)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--serve-n", type=int, default=32)
+    ap.add_argument("--serve-n", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-tol", type=float, default=1e-7)
     ap.add_argument("--serve-max-steps", type=int, default=100000)
@@ -231,11 +442,13 @@ def main():
     ap.add_argument("--serve-order", default="smallest", choices=["smallest", "fifo"])
     ap.add_argument("--serve-window", type=int, default=4 << 20,
                     help="cap on resident fluid nodes in the pool (0: none)")
+    ap.add_argument("--serve-below-n", type=int, default=24,
+                    help="requests of the run at 0.7 x the measured saturation rate (0: skip)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-no-baseline", action="store_true",
-                    help="skip serving the trace one request at a time")
+    ap.add_argument("--serve-baseline", action="store_true",
+                    help="also serve the trace one request at a time")
     ap.add_argument("--single-launches", action="store_true",
-                    help="one kernel launch per step instead of 100-step graphs")
+                    help="one kernel launch per step instead of graph replays")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times "
                          "(reference for the HBM byte counters)")
@@ -264,47 +477,14 @@ def main():
     case = I.rotating_lid_cylinder(Nr=args.Nr, Nz=args.Nz, Re=1000.0, Ri=0.5,
                                    u_noise=args.u_noise)
     nodes = case["Nr"] * case["Nz"]
-    stream = torch.cuda.Stream()
-    lat = axlb.Lattice(case, storage=args.storage, layout=args.layout, stream=stream,
-                       deriv=args.deriv)
-    print("bench: %dx%d %s %s, warmup %d" % (args.Nr, args.Nz, args.storage, args.layout,
-                                             args.warmup), file=sys.stderr, flush=True)
-    if args.tile >= 0:
-        lat.set_tile(args.tile)
-        tune = None
-    else:
-        best, ms = lat.autotune(steps_per_trial=40)
-        tune = {"%dx%d" % axlb.tile_shape(t): round(m * 1e3, 2) for t, m in enumerate(ms)}
-        print("bench: autotune us/step per tile %s" % tune, file=sys.stderr, flush=True)
-    tile_id, tile_rz = lat.tile()
-    lat.step(args.warmup)
-    lat.sync()
-    torch.cuda.synchronize()
-
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record(stream)
-    if args.single_launches:
-        for _ in range(args.steps):
-            lat.step(1)
-    else:
-        lat.step(args.steps)
-    end.record(stream)
-    end.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end)
-    ms_per_step = ms / args.steps
-    mlups = nodes * args.steps / (ms / 1e3) / 1e6
+    h = headline(args, case, torch.cuda.Stream())
+    ms_per_step = h["ms_per_step"]
     achieved = BYTES_PER_UPDATE[args.storage] * nodes / (ms_per_step / 1e3) / 1e9
-    r = lat.residual()
-    print("bench: timed %d steps in %.3f s (events %.3f ms/step)" % (args.steps, wall, ms_per_step),
-          file=sys.stderr, flush=True)
+    working_set = step_working_set(args.Nr, args.Nz, args.storage, args.layout)
 
     out = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": round(h["mlups"], 1),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -319,28 +499,61 @@ def main():
                    "initial_noise": {"T": 1e-4, "u": args.u_noise},
                    "Nr": args.Nr, "Nz": args.Nz, "storage": args.storage,
                    "layout": args.layout, "derivatives": args.deriv,
-                   "graph_bundle": 0 if args.single_launches else 100,
-                   "tile": "%dx%d" % tile_rz, "autotune_us_per_step": tune},
+                   "lag_storage": ("u_z, u_r, u_theta, T - T_ref as FP32: 16 B per node "
+                                   "written and read per step" if args.storage == "f32" else
+                                   "u_z, u_r, u_theta as binary16 (x 2^10), T - T_ref as FP32: "
+                                   "10 B per node written and read per step"),
+                   "launch": h["launch"],
+                   "tile": h["tile"], "autotune_us_per_step": h["autotune_us_per_step"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": (measured_traffic(args.storage, args.Nr, args.Nz)
-                                 if args.layout == "aa" and args.deriv == "lagged" else None)},
-        "finite": bool(r == r),
+                                 if args.layout == "aa" and args.deriv == "lagged" else None),
+                     "working_set_bytes": working_set,
+                     "cache_resident": working_set < 256e6,
+                     "note": "algorithmic bytes (%d B per node update) over the measured step "
+                             "time; the state plus lagged fields %s the 256 MB Infinity Cache, "
+                             "see out_of_cache for a lattice that does not fit"
+                             % (BYTES_PER_UPDATE[args.storage],
+                                "fit in" if working_set < 256e6 else "exceed")},
+        "finite": h["finite"],
     }
-    lat.close()
+    if args.ooc_Nr > 0:
+        print("bench: out-of-cache %dx%d" % (args.ooc_Nr, args.ooc_Nz), file=sys.stderr,
+              flush=True)
+        out["out_of_cache"] = out_of_cache(args.ooc_Nr, args.ooc_Nz, args.ooc_steps, args.storage)
+    gpu_accuracy = None
+    if not args.no_accuracy:
+        print("bench: accuracy runs", file=sys.stderr, flush=True)
+        gpu_accuracy = accuracy_runs()
     if not args.no_batch:
         print("bench: batched, %d instances" % args.batch_n, file=sys.stderr, flush=True)
-        out["batched"] = bench_batched(args.batch_n, args.batch_steps, 200, 100)
+        out["batched"] = bench_batched(args.batch_n, args.batch_steps, 200, args.batch_steps)
     if not args.no_serve:
         print("bench: served, %d requests" % args.serve_n, file=sys.stderr, flush=True)
-        out["served"] = bench_served(args.serve_n, args.serve_rate, args.serve_tol,
-                                     args.serve_max_steps, args.serve_budget_gib,
-                                     args.serve_max_nr_log2, args.serve_max_nz_log2,
-                                     args.serve_order, args.serve_window,
-                                     baseline=not args.serve_no_baseline)
-    if not args.no_cpu_baseline:
-        print("bench: oracle CPU baseline, %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+        served = bench_served(args.serve_n, args.serve_rate, args.serve_tol,
+                              args.serve_max_steps, args.serve_budget_gib,
+                              args.serve_max_nr_log2, args.serve_max_nz_log2,
+                              args.serve_order, args.serve_window,
+                              baseline=args.serve_baseline)
+        served["note"] = ("queue-dominated: all %d requests arrive within %.2f s, far faster "
+                          "than they can be served" % (args.serve_n, served["arrival_span_s"]))
+        if args.serve_below_n > 0:
+            rate = 0.7 * served["solves_per_s"]
+            print("bench: served below saturation, %d requests at %.3f/s"
+                  % (args.serve_below_n, rate), file=sys.stderr, flush=True)
+            served["below_saturation"] = bench_served(
+                args.serve_below_n, rate, args.serve_tol, args.serve_max_steps,
+                args.serve_budget_gib, args.serve_max_nr_log2, args.serve_max_nz_log2,
+                args.serve_order, args.serve_window, baseline=False)
+        out["served"] = served
+    if not args.no_cpu_baseline or gpu_accuracy is not None:
+        print("bench: oracle on the host", file=sys.stderr, flush=True)
+        base, acc = cpu_leg(case, args.cpu_steps, args.cpu_steps_all, gpu_accuracy)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = base
+        if acc is not None:
+            out["accuracy"] = acc
     print(json.dumps(out), flush=True)
 
 

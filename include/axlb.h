@@ -178,8 +178,17 @@ int axlb_set_body_force(axlb_lattice *lat, double g_axial, double T0);
 int axlb_set_fields(axlb_lattice *lat, const double *rho, const double *ur, const double *uz,
                     const double *uth, const double *T);
 
-/* Enqueues n time steps on the lattice's stream (asynchronous). */
+/* Enqueues n time steps on the lattice's stream (asynchronous).  The steps
+ * run as replays of captured HIP graphs: bundles of 100 steps, then one
+ * graph of the remaining steps (a single remaining step is a plain launch).
+ * A graph is captured the first time its length and starting phase occur
+ * and is kept with the lattice (the 100-step bundles always, at most 8
+ * other lengths).  Results are identical to one launch per step. */
 int axlb_step(axlb_lattice *lat, long n);
+/* Captures, without running them, the graphs that axlb_step(lat, n) would
+ * replay from the current state, so that a timed or latency-bound call
+ * does not pay for the capture.  AXLB_ESTATE for a batch member. */
+int axlb_prepare_steps(axlb_lattice *lat, long n);
 long axlb_steps_done(const axlb_lattice *lat);
 /* Waits for the lattice's stream. */
 int axlb_sync(axlb_lattice *lat);
@@ -224,7 +233,11 @@ int axlb_set_tile(axlb_lattice *lat, int tile);
 int axlb_get_tile(const axlb_lattice *lat, int *tile, int *tile_r, int *tile_z);
 int axlb_autotune(axlb_lattice *lat, int steps_per_trial, double *ms_per_step, int *best);
 
-void axlb_destroy(axlb_lattice *lat);
+/* Releases the lattice and the device memory the library allocated for it
+ * (memory lent through device_buf stays the caller's).  AXLB_ESTATE, with
+ * nothing released, while the lattice is a member of a batch: the batch
+ * would go on stepping its memory.  NULL is a no-op. */
+int axlb_destroy(axlb_lattice *lat);
 
 /* ---- slabs of one lattice (a lattice cut along z, one piece per GPU) ----
  * A slab's cut faces have kind AXLB_HALO.  Before each step, the row of

@@ -42,6 +42,7 @@ EXPORTS = [
     "axlb_pool_create", "axlb_pool_set_policy", "axlb_pool_submit", "axlb_pool_tick",
     "axlb_pool_status",
     "axlb_pool_result", "axlb_pool_usage", "axlb_pool_destroy", "axlb_pool_last_error",
+    "axlb_prepare_steps",
 ]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 POOL_ORDER = {"fifo": 0, "smallest": 1}
@@ -106,6 +107,7 @@ def load():
         "axlb_set_body_force": ([_vp, C.c_double, C.c_double], C.c_int),
         "axlb_set_fields": ([_vp] + [_dp] * 5, C.c_int),
         "axlb_step": ([_vp, C.c_long], C.c_int),
+        "axlb_prepare_steps": ([_vp, C.c_long], C.c_int),
         "axlb_steps_done": ([_vp], C.c_long),
         "axlb_sync": ([_vp], C.c_int),
         "axlb_get_moments": ([_vp] + [_dp] * 5, C.c_int),
@@ -114,7 +116,7 @@ def load():
         "axlb_state_size": ([_vp, C.POINTER(C.c_size_t)], C.c_int),
         "axlb_save": ([_vp, _vp, C.c_size_t], C.c_int),
         "axlb_load": ([_vp, _vp, C.c_size_t], C.c_int),
-        "axlb_destroy": ([_vp], None),
+        "axlb_destroy": ([_vp], C.c_int),
         "axlb_tile_shape": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "axlb_set_tile": ([_vp, C.c_int], C.c_int),
         "axlb_get_tile": ([_vp] + [C.POINTER(C.c_int)] * 3, C.c_int),
@@ -234,8 +236,10 @@ class Lattice:
             raise AxlbError(rc, self._lib.axlb_last_error(self._h).decode())
 
     def close(self):
+        """Releases the lattice.  Raises AxlbError (and keeps the lattice and
+        its memory) while it is a member of a live batch."""
         if self._h:
-            self._lib.axlb_destroy(self._h)
+            self._check(self._lib.axlb_destroy(self._h))
             self._h = _vp()
         self._buf = None
 
@@ -256,6 +260,10 @@ class Lattice:
 
     def step(self, n: int = 1):
         self._check(self._lib.axlb_step(self._h, int(n)))
+
+    def prepare_steps(self, n: int):
+        """Captures the graphs that step(n) would replay from here."""
+        self._check(self._lib.axlb_prepare_steps(self._h, int(n)))
 
     def sync(self):
         self._check(self._lib.axlb_sync(self._h))

@@ -29,13 +29,14 @@ Layout layout_for(int Nr, int Nz, int storage, int layout) {
     const size_t a = 256;
     auto up = [&](size_t b) { return (b + a - 1) / a * a; };
     L.pop_bytes = up((size_t)NPOP * L.plane * storage_size(storage));
-    L.lag_bytes = up(LAG_NODE_BYTES * L.plane);
+    const int vb = lag_vb(storage);
+    L.lag_bytes = up(lag_node_bytes(vb) * L.plane);
     const size_t N = (size_t)Nr * Nz;
     L.fld_bytes = up(5 * N * sizeof(double));
     L.snap_bytes = up(4 * N * sizeof(double));
     L.red_bytes = up((RED_BLOCKS * 9 + 16) * sizeof(double));
     L.halo_pop_bytes = up((size_t)NPOP * L.pitch * storage_size(storage));
-    L.halo_lag_bytes = up(LAG_NODE_BYTES * L.pitch);
+    L.halo_lag_bytes = up(lag_node_bytes(vb) * L.pitch);
     L.total = (layout == AXLB_LAYOUT_AA ? 1 : 2) * L.pop_bytes + 2 * L.lag_bytes + L.fld_bytes +
               L.snap_bytes + L.red_bytes + 2 * (L.halo_pop_bytes + L.halo_lag_bytes);
     return L;
@@ -99,7 +100,7 @@ KParams axlb::make_params(const axlb_lattice *L) {
         }
     for (int f = 0; f < 2; ++f) {
         P.halo_pop[f] = L->halo[f];
-        P.halo_lag[f] = (const LagT *)(L->halo[f] + L->lay.halo_pop_bytes);
+        P.halo_lag[f] = L->halo[f] + L->lay.halo_pop_bytes;
     }
     return P;
 }
@@ -166,23 +167,45 @@ static int launch_one(axlb_lattice *L) {
     return AXLB_OK;
 }
 
-// Key of the graph that runs the next bundle: the AA phase, or the buffer
-// the two-buffer layouts read (a bundle flips it an even number of times).
+// Key of the graph that runs the next steps: the AA phase, or the buffer
+// the two-buffer layouts read.  A BUNDLE of steps flips either an even
+// number of times (BUNDLE is a multiple of 4), so every bundle of a call
+// shares the key of the call's first step.
 static int graph_key(const axlb_lattice *L) {
     return two_buffers(L) ? L->cur : (int)(L->steps & 1);
 }
 
-// HIP graph of BUNDLE consecutive steps for graph key k (see graph_key);
-// BUNDLE is even (and a multiple of 4), so every buffer role recurs.
-static int ensure_graph(axlb_lattice *L, int k) {
-    if (L->graph_exec[k]) return AXLB_OK;
+// Graphs of other lengths than BUNDLE (the tail of an axlb_step call) kept
+// per lattice; beyond this many the cached tails are dropped first.
+constexpr size_t MAX_TAIL_GRAPHS = 8;
+
+static void drop_graphs(axlb_lattice *L, bool tails_only = false) {
+    for (auto it = L->graphs.begin(); it != L->graphs.end();) {
+        if (tails_only && it->first.first == BUNDLE) {
+            ++it;
+            continue;
+        }
+        (void)hipGraphExecDestroy(it->second);
+        it = L->graphs.erase(it);
+    }
+}
+
+// HIP graph of `len` consecutive steps for graph key k (see graph_key):
+// the launches a plain run would make, two steps per launch in the
+// two-step layout (an odd length ends with one single step).
+static int ensure_graph(axlb_lattice *L, long len, int k) {
+    const auto key = std::make_pair(len, k);
+    if (L->graphs.count(key)) return AXLB_OK;
+    if (len != BUNDLE && L->graphs.size() >= MAX_TAIL_GRAPHS) drop_graphs(L, true);
     HIP_TRY(L, hipStreamBeginCapture(L->stream, hipStreamCaptureModeThreadLocal));
     int rc = AXLB_OK;
     const bool two = L->layout == AXLB_LAYOUT_AB2;
     int cur = k;
-    for (long s = 0; s < BUNDLE && rc == AXLB_OK; s += two ? 2 : 1) {
-        rc = launch_steps(L, k + s, cur, two);  // for AA, k + s has the parity of the step
+    for (long s = 0; s < len && rc == AXLB_OK;) {
+        const bool pair = two && s + 1 < len;
+        rc = launch_steps(L, k + s, cur, pair);  // for AA, k + s has the parity of the step
         cur ^= 1;
+        s += pair ? 2 : 1;
     }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(L->stream, &g);
@@ -191,21 +214,13 @@ static int ensure_graph(axlb_lattice *L, int k) {
         return rc;
     }
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&L->graph_exec[k], g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        L->graph_exec[k] = nullptr;
+    if (e != hipSuccess)
         return fail(L, AXLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-    }
+    L->graphs[key] = x;
     return AXLB_OK;
-}
-
-static void drop_graphs(axlb_lattice *L) {
-    for (int k = 0; k < 2; ++k)
-        if (L->graph_exec[k]) {
-            (void)hipGraphExecDestroy(L->graph_exec[k]);
-            L->graph_exec[k] = nullptr;
-        }
 }
 
 static int set_device(axlb_lattice *L) {
@@ -353,9 +368,9 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     } else {
         L->pop[1] = L->pop[0];
     }
-    L->lag[0] = (LagT *)p;
+    L->lag[0] = p;
     p += L->lay.lag_bytes;
-    L->lag[1] = (LagT *)p;
+    L->lag[1] = p;
     p += L->lay.lag_bytes;
     L->fld = (double *)p;
     p += L->lay.fld_bytes;
@@ -458,13 +473,20 @@ int axlb_step(axlb_lattice *L, long n) {
     int rc = lattice_start(L);
     if (rc) return rc;
     while (n > 0) {
-        if (n >= BUNDLE && L->use_graphs) {
+        if (L->use_graphs && n >= 2) {
+            // a bundle, or the whole tail of the call, as one graph replay
+            const long len = n >= BUNDLE ? BUNDLE : n;
             const int k = graph_key(L);
-            rc = ensure_graph(L, k);
+            rc = ensure_graph(L, len, k);
             if (rc) return rc;
-            HIP_TRY(L, hipGraphLaunch(L->graph_exec[k], L->stream));
-            L->steps += BUNDLE;
-            n -= BUNDLE;
+            HIP_TRY(L, hipGraphLaunch(L->graphs[std::make_pair(len, k)], L->stream));
+            L->steps += len;
+            if (two_buffers(L)) {
+                // buffers swap once per launch
+                const long launches = L->layout == AXLB_LAYOUT_AB2 ? (len + 1) / 2 : len;
+                if (launches & 1) L->cur ^= 1;
+            }
+            n -= len;
         } else if (n >= 2 && L->layout == AXLB_LAYOUT_AB2) {
             rc = launch_steps(L, L->steps, L->cur, true);
             if (rc) return rc;
@@ -478,6 +500,20 @@ int axlb_step(axlb_lattice *L, long n) {
         }
     }
     return AXLB_OK;
+}
+
+int axlb_prepare_steps(axlb_lattice *L, long n) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (n < 0) return fail(L, AXLB_EINVAL, "negative step count");
+    if (L->batched) return fail(L, AXLB_ESTATE, "the lattice steps through its batch");
+    int rc = lattice_start(L);
+    if (rc || !L->use_graphs) return rc;
+    // the graphs axlb_step(n) replays from the current state: its bundles
+    // and its tail share the key of the first step
+    const int k = graph_key(L);
+    if (n >= BUNDLE) rc = ensure_graph(L, BUNDLE, k);
+    if (rc == AXLB_OK && n % BUNDLE >= 2) rc = ensure_graph(L, n % BUNDLE, k);
+    return rc;
 }
 
 long axlb_steps_done(const axlb_lattice *L) { return L ? L->steps : -1; }
@@ -648,15 +684,18 @@ int axlb_load(axlb_lattice *L, const void *host, size_t bytes) {
     return AXLB_OK;
 }
 
-void axlb_destroy(axlb_lattice *L) {
-    if (!L || L->batched) return;  // a member is released with its batch
+int axlb_destroy(axlb_lattice *L) {
+    if (!L) return AXLB_OK;
+    // a batch keeps stepping its members' memory: refuse until it is gone
+    if (L->batched)
+        return fail(L, AXLB_ESTATE, "the lattice is in a batch: destroy the batch first");
     (void)hipSetDevice(L->device);
     if (L->stream) (void)hipStreamSynchronize(L->stream);
-    for (int k = 0; k < 2; ++k)
-        if (L->graph_exec[k]) (void)hipGraphExecDestroy(L->graph_exec[k]);
+    drop_graphs(L);
     if (L->own_mem && L->base) (void)hipFree(L->base);
     if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
     delete L;
+    return AXLB_OK;
 }
 
 int axlb_set_tile(axlb_lattice *L, int tile) {
@@ -771,13 +810,14 @@ int axlb_halo_export(axlb_lattice *L, int face, void *device_dst) {
     const char *pop = (const char *)L->pop[L->cur] + row * pitch * es;
     HIP_TRY(L, hipMemcpy2DAsync(dst, pitch * es, pop, plane * es, L->Nr * es, NPOP,
                                 hipMemcpyDeviceToDevice, L->stream));
-    const char *lag = (const char *)L->lag[L->cur];
+    // the halo row's lagged fields use the block layout with pitch-element
+    // planes: three velocity planes of vb-byte elements, then T in FP32
+    const char *lag = L->lag[L->cur];
     char *hl = dst + L->lay.halo_pop_bytes;
-    HIP_TRY(L, hipMemcpy2DAsync(hl, pitch * sizeof(LagT), lag + row * pitch * sizeof(LagT),
-                                plane * sizeof(LagT), L->Nr * sizeof(LagT), 3,
+    const size_t vb = lag_vb(L->storage);
+    HIP_TRY(L, hipMemcpy2DAsync(hl, pitch * vb, lag + row * pitch * vb, plane * vb, L->Nr * vb, 3,
                                 hipMemcpyDeviceToDevice, L->stream));
-    HIP_TRY(L, hipMemcpyAsync(hl + 3 * pitch * sizeof(LagT),
-                              lag + 3 * plane * sizeof(LagT) + row * pitch * sizeof(float),
+    HIP_TRY(L, hipMemcpyAsync(hl + 3 * pitch * vb, lag + 3 * plane * vb + row * pitch * sizeof(float),
                               L->Nr * sizeof(float), hipMemcpyDeviceToDevice, L->stream));
     return AXLB_OK;
 }

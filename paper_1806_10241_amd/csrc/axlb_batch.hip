@@ -34,7 +34,7 @@ constexpr size_t GROUP_BYTES = 80u << 20;
 struct InstDesc {
     KParams P;
     void *pop;
-    LagT *lag[2];
+    char *lag[2];     // lagged-field blocks (format of the storage type)
     int parity0;     // member step count at batch creation, mod 2
     int tile_begin;  // first work-list entry of this member
     int gx;          // tiles along r

@@ -121,8 +121,7 @@ static hipError_t step_current_t(const KParams &P, int tile, const void *src, vo
                                  hipStream_t st) {
     const S *a = (const S *)src;
     S *b = (S *)dst;
-    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, MODE_AB, src, dst,
-                                 nullptr, nullptr);
+    const Planes A = step_planes(P, store_of<S>(), MODE_AB, src, dst, nullptr, nullptr);
     switch (tile) {
 #define AXLB_CASE(id, bx, by)                                                                 \
     case id:                                                                                  \
@@ -139,8 +138,8 @@ static hipError_t step_current_t(const KParams &P, int tile, const void *src, vo
 template <class S>
 static hipError_t fields_current_t(const KParams &P, const void *src, double *out, hipStream_t st) {
     // reads only: the write planes are never used
-    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, MODE_AB, src,
-                                 const_cast<void *>(src), nullptr, nullptr);
+    const Planes A = step_planes(P, store_of<S>(), MODE_AB, src, const_cast<void *>(src),
+                                 nullptr, nullptr);
     k_current<S, 64, 4, false><<<dim3(((P.Nr + 63) / 64) * ((P.Nz + 3) / 4)), dim3(256), 0, st>>>(
         P, A, (const S *)src, nullptr, out);
     return hipGetLastError();

@@ -17,46 +17,71 @@ enum { NOSLIP = 0, PERIODIC = 1, MIRROR = 2, DIRICHLET = 3, OMEGA_R = 4, ADIABAT
 constexpr int NPOP = 19;
 constexpr int GOFF = 9;
 constexpr int HOFF = 14;
-// Lagged derivative fields, one block per time level: planes 0..2 hold
-// u_x, u_y, u_theta in binary16 scaled by 2^10 (values down to ~6e-8 stay
-// clear of subnormals, |values| up to 64 fit), plane 3 holds T - T_ref in
-// FP32.  They are rewritten every step, so their rounding never
-// accumulates, and they only enter the central differences of the
-// geometric sources.  Temperature keeps FP32: its gradient at the walls is
-// the Nusselt number, and binary16 (relative step 2^-11 on values up to
-// 1/2) would bias it at steady state.
+// Lagged derivative fields, one block per time level: four planes of
+// `plane` elements, u_x, u_y, u_theta and T - T_ref.  They are rewritten
+// every step and only enter the central differences of the geometric
+// sources.  The block is addressed as bytes; its element format follows the
+// population storage (LagFmt):
+//  * FP32 populations: all four planes FP32 (16 B per node), so that the
+//    FP32 path holds FP32 state throughout.  binary16 velocities were
+//    measured to cost up to 1e-5 of the speed in u_z near the axis of a
+//    cylinder, where the radial differences are divided by r.
+//  * 16-bit populations: u_x, u_y, u_theta in binary16 scaled by 2^10
+//    (values down to ~6e-8 stay clear of subnormals, |values| up to 64 fit),
+//    T - T_ref in FP32 (10 B per node): the velocity rounding stays far
+//    below the 16-bit populations' own, while T keeps FP32 because its wall
+//    gradient is the Nusselt number.
+// Plane 3 (T) starts at byte 3 * plane * VB, 4-byte aligned since plane is
+// a multiple of 64.
 constexpr int NLAG = 4;
-using LagT = __half;
 constexpr float LAG_SCALE = 1024.f;
-constexpr size_t LAG_NODE_BYTES = 3 * sizeof(__half) + sizeof(float);
-__device__ __forceinline__ const float *lag_T(const LagT *M, long long plane) {
-    return reinterpret_cast<const float *>(M + 3 * plane);
-}
-__device__ __forceinline__ float *lag_T(LagT *M, long long plane) {
-    return reinterpret_cast<float *>(M + 3 * plane);
-}
+
 // Scaled binary16 -> FP32 as one mixed-precision FMA (v_fma_mix_f32: the
 // binary16 operand is widened inside the instruction); adding +0 instead of
 // multiplying only turns a -0 result into +0.
 __device__ __forceinline__ float f16_scaled(__half h, float s) {
     return __builtin_fmaf(__half2float(h), s, 0.f);
 }
-__device__ __forceinline__ float lag_h(const LagT *p) { return f16_scaled(*p, 1.f / LAG_SCALE); }
+
+// Element format of the velocity planes for population storage S: Bits is
+// the stored word, VB its size in bytes, enc/dec convert from/to FP32.
+template <class S> struct LagFmt {
+    using Bits = unsigned short;
+    static constexpr int VB = 2;
+    __device__ static __forceinline__ float dec(Bits b) {
+        return f16_scaled(__builtin_bit_cast(__half, b), 1.f / LAG_SCALE);
+    }
+    __device__ static __forceinline__ Bits enc(float x) {
+        return __builtin_bit_cast(unsigned short, __float2half_rn(x * LAG_SCALE));
+    }
+};
+template <> struct LagFmt<float> {
+    using Bits = float;
+    static constexpr int VB = 4;
+    __device__ static __forceinline__ float dec(Bits b) { return b; }
+    __device__ static __forceinline__ Bits enc(float x) { return x; }
+};
+// Bytes per node of one block, by velocity element size.
+__host__ __device__ constexpr size_t lag_node_bytes(int vb) { return 3 * (size_t)vb + 4; }
+
 // Field v at element offset off of a block with the given plane size.
-template <class I>
-__device__ __forceinline__ float lag_ld(const LagT *M, int v, long long plane, I off) {
-    if (v == 3) return lag_T(M, plane)[off];
-    return lag_h(M + v * plane + off);
+template <class S, class I>
+__device__ __forceinline__ float lag_ld(const char *M, int v, long long plane, I off) {
+    using F = LagFmt<S>;
+    if (v == 3) return reinterpret_cast<const float *>(M + 3 * plane * F::VB)[off];
+    return F::dec(reinterpret_cast<const typename F::Bits *>(M + v * plane * F::VB)[off]);
 }
-template <class I>
-__device__ __forceinline__ void lag_st(LagT *M, int v, long long plane, I off, float x) {
-    if (v == 3) lag_T(M, plane)[off] = x;
-    else M[v * plane + off] = __float2half_rn(x * LAG_SCALE);
+template <class S, class I>
+__device__ __forceinline__ void lag_st(char *M, int v, long long plane, I off, float x) {
+    using F = LagFmt<S>;
+    if (v == 3) reinterpret_cast<float *>(M + 3 * plane * F::VB)[off] = x;
+    else reinterpret_cast<typename F::Bits *>(M + v * plane * F::VB)[off] = F::enc(x);
 }
 // The value lag_ld returns after lag_st stored x in field v.
+template <class S>
 __device__ __forceinline__ float lag_round(int v, float x) {
     if (v == 3) return x;
-    return f16_scaled(__float2half_rn(x * LAG_SCALE), 1.f / LAG_SCALE);
+    return LagFmt<S>::dec(LagFmt<S>::enc(x));
 }
 
 // Everything a step kernel needs, passed by value.
@@ -77,7 +102,7 @@ struct KParams {
     // storage type, then its lagged fields as a block of `pitch`-element
     // planes (lag_ld layout)
     const void *halo_pop[2];
-    const LagT *halo_lag[2];
+    const char *halo_lag[2];
 };
 
 // Plane addresses of one step launch, for the tile workgroups of the step

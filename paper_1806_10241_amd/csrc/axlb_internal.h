@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <string>
+#include <utility>
 
 #include "../../include/axlb.h"
 #include "axlb_device.h"
@@ -41,10 +43,11 @@ struct axlb_lattice {
     axlb::Layout lay{};
     char *base = nullptr;
     void *pop[2] = {nullptr, nullptr};
-    axlb::LagT *lag[2] = {nullptr, nullptr};
+    char *lag[2] = {nullptr, nullptr};  // lagged-field blocks (byte addressed)
     double *fld = nullptr, *snap = nullptr, *red = nullptr;
     char *halo[2] = {nullptr, nullptr};  // halo rows of the z faces (HALO kind)
-    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    // captured step sequences: (steps in the graph, graph key) -> executable
+    std::map<std::pair<long, int>, hipGraphExec_t> graphs;
     bool use_graphs = true;
     int tile = 0;  // step-kernel tile shape (see tile_shape)
     bool started = false, has_snap = false;

@@ -6,8 +6,9 @@
 // `pitch`): 19 population planes pop[q][iz][ir] holding shifted populations
 // f - w_q (rho_0 = 1), g, and h - w_q T_ref, in FP32, binary16 or bfloat16,
 // and two blocks (time levels) of lagged derivative fields, each three
-// binary16 velocity planes and one FP32 temperature plane.  All arithmetic
-// is FP32; reductions are FP64.
+// velocity planes (FP32 with FP32 populations, scaled binary16 with 16-bit
+// ones) and one FP32 temperature plane.  All arithmetic is FP32; reductions
+// are FP64.
 //
 // Streaming layouts:
 //  * AA (one buffer, in place).  Even phase: node n reads its own slots
@@ -20,6 +21,7 @@
 #include "axlb_device.h"
 #include "axlb_launch.h"
 #include "axlb_node.h"
+#include "axlb_reduce.h"
 
 namespace axlb {
 
@@ -40,8 +42,8 @@ constexpr int EDGE_PER_BLOCK = 64;
 template <class S, int MODE, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const Planes A,
                                                    const S *src, S *dst,
-                                                   const LagT *__restrict__ Mprev,
-                                                   LagT *__restrict__ Mnext) {
+                                                   const char *__restrict__ Mprev,
+                                                   char *__restrict__ Mnext) {
     constexpr bool SPLIT = MODE != MODE_AA_EVEN;
     const int gx = (P.Nr + BX - 1) / BX;
     const int ne = SPLIT ? edge_blocks(P.Nr, P.Nz, EDGE_PER_BLOCK) : 0;
@@ -73,7 +75,7 @@ __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const Planes 
 // out = [rho, u_r, u_z, u_theta, T] planes of Nz*Nr doubles.
 template <class S, int MODE>
 __global__ void __launch_bounds__(TX * TY) k_fields(const KParams P, const S *src,
-                                                     const LagT *__restrict__ Mprev,
+                                                     const char *__restrict__ Mprev,
                                                      double *__restrict__ out) {
     int i, j;
     tile_of<TX, TY>(P, i, j);
@@ -83,7 +85,7 @@ __global__ void __launch_bounds__(TX * TY) k_fields(const KParams P, const S *sr
     gather<S, MODE>(P, src, i, j, interior, f, g, h);
     const Moments m = moments(f, g, h);
     float d[5];
-    derivatives(P, Mprev, i, j, interior, d);
+    derivatives<S>(P, Mprev, i, j, interior, d);
     const float iy = rcp(P.r0 + (float)j + 0.5f);
     const Half H = half_step(P, iy, m.drho, m.jx, m.jy, m.psi, m.dphi, d);
     const long long N = (long long)P.Nr * P.Nz, k = (long long)i * P.Nr + j;
@@ -107,7 +109,7 @@ __device__ __forceinline__ double w1(int e, double u) {
 
 template <class S, bool AA>
 __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
-                                                   const double *__restrict__ in, LagT *M) {
+                                                   const double *__restrict__ in, char *M) {
     int i, j;
     tile_of<TX, TY>(P, i, j);
     if (i >= P.Nz || j >= P.Nr) return;
@@ -144,38 +146,16 @@ __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
         Conv<S>::st(A + (HOFF + slot) * P.plane + n, (float)(he[q] - w * Tref),
                     skey(i, j, HOFF + q));
     }
-    lag_st(M, 0, P.plane, n, (float)uz);
-    lag_st(M, 1, P.plane, n, (float)ur);
-    lag_st(M, 2, P.plane, n, (float)uth);
-    lag_st(M, 3, P.plane, n, (float)(T - Tref));
+    lag_st<S>(M, 0, P.plane, n, (float)uz);
+    lag_st<S>(M, 1, P.plane, n, (float)ur);
+    lag_st<S>(M, 2, P.plane, n, (float)uth);
+    lag_st<S>(M, 3, P.plane, n, (float)(T - Tref));
 }
 
 // ----------------------------------------------------------------------------
 // FP64 reductions.  Block sums are formed with wavefront shuffles and LDS in
-// a fixed order, and the per-block partials are summed by one workgroup in
-// block order, so the result does not depend on scheduling.
-constexpr int RED_THREADS = 256;
-
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double *sh /* [K][RED_THREADS/64] */) {
-#pragma unroll
-    for (int c = 0; c < K; ++c) {
-        double x = v[c];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        v[c] = x;
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0)
-        for (int c = 0; c < K; ++c) sh[c * (RED_THREADS / 64) + w] = v[c];
-    __syncthreads();
-    if (threadIdx.x == 0)
-        for (int c = 0; c < K; ++c) {
-            double s = 0.0;
-            for (int k = 0; k < RED_THREADS / 64; ++k) s += sh[c * (RED_THREADS / 64) + k];
-            v[c] = s;
-        }
-}
+// a fixed order (block_sum), and the per-block partials are summed by one
+// workgroup in block order, so the result does not depend on scheduling.
 
 // Residual partials: for the four fields u_r, u_z, u_theta, T (planes 1..4
 // of `fld`) the sums of (q - snap)^2 and q^2, plus the count of non-finite
@@ -280,7 +260,7 @@ static void plane_offsets(const KParams &P, int mode, int q, long long &rd, long
 // a read address of the odd phase or the pull may lie before its plane
 // (the node offset brings it back inside for every node that uses it).
 Planes step_planes(const KParams &P, int storage, int mode, const void *src, void *dst,
-                   const LagT *Mprev, LagT *Mnext) {
+                   const char *Mprev, char *Mnext) {
     Planes A{};
     const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
     const long long es = storage == STORE_F32 ? 4 : 2;
@@ -301,23 +281,23 @@ Planes step_planes(const KParams &P, int storage, int mode, const void *src, voi
     }
     // the lagged-field planes (left null for launches without them)
     if (Mprev && Mnext) {
+        const long long vb = storage == STORE_F32 ? 4 : 2;  // velocity element size
         for (int v = 0; v < NLAG; ++v) {
-            A.lrd[v] = (const char *)(Mprev + v * P.plane);
-            A.lwr[v] = (char *)(Mnext + v * P.plane);
+            A.lrd[v] = Mprev + v * P.plane * vb;
+            A.lwr[v] = Mnext + v * P.plane * vb;
         }
-        A.uy_up = (const char *)((uintptr_t)A.lrd[1] + (uintptr_t)(2 * P.pitch));
-        A.uy_dn = (const char *)((uintptr_t)A.lrd[1] - (uintptr_t)(2 * P.pitch));
+        A.uy_up = (const char *)((uintptr_t)A.lrd[1] + (uintptr_t)(vb * P.pitch));
+        A.uy_dn = (const char *)((uintptr_t)A.lrd[1] - (uintptr_t)(vb * P.pitch));
     }
     return A;
 }
 
 template <class S, int BX, int BY>
-static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT *Mprev,
-                             LagT *Mnext, hipStream_t st) {
+static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const char *Mprev,
+                             char *Mnext, hipStream_t st) {
     const int edges = mode == MODE_AA_EVEN ? 0 : edge_blocks(P.Nr, P.Nz, EDGE_PER_BLOCK);
     const dim3 grid(grid_for(P, BX, BY).x + edges), block(BX * BY);
-    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, mode, a,
-                                 mode == MODE_AB ? b : a, Mprev, Mnext);
+    const Planes A = step_planes(P, store_of<S>(), mode, a, mode == MODE_AB ? b : a, Mprev, Mnext);
     switch (mode) {
     case MODE_AB: k_step<S, MODE_AB, BX, BY><<<grid, block, 0, st>>>(P, A, a, b, Mprev, Mnext); break;
     case MODE_AA_ODD: k_step<S, MODE_AA_ODD, BX, BY><<<grid, block, 0, st>>>(P, A, a, a, Mprev, Mnext); break;
@@ -327,7 +307,7 @@ static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const LagT 
 
 template <class S>
 static hipError_t launch_step_t(const KParams &P, int tile, int mode, void *src, void *dst,
-                                const LagT *Mprev, LagT *Mnext, hipStream_t st) {
+                                const char *Mprev, char *Mnext, hipStream_t st) {
     S *a = (S *)src, *b = (S *)dst;
     switch (tile) {
 #define AXLB_CASE(id, bx, by) \
@@ -340,7 +320,7 @@ static hipError_t launch_step_t(const KParams &P, int tile, int mode, void *src,
 }
 
 template <class S>
-static hipError_t launch_fields_t(const KParams &P, int mode, const void *src, const LagT *Mprev,
+static hipError_t launch_fields_t(const KParams &P, int mode, const void *src, const char *Mprev,
                                   double *out, hipStream_t st) {
     const dim3 grid = step_grid(P), block(TX * TY);
     const S *a = (const S *)src;
@@ -353,7 +333,7 @@ static hipError_t launch_fields_t(const KParams &P, int mode, const void *src, c
 }
 
 template <class S>
-static hipError_t launch_init_t(const KParams &P, bool aa, void *pop, const double *in, LagT *M,
+static hipError_t launch_init_t(const KParams &P, bool aa, void *pop, const double *in, char *M,
                                 hipStream_t st) {
     const dim3 grid = step_grid(P), block(TX * TY);
     if (aa) k_init<S, true><<<grid, block, 0, st>>>(P, (S *)pop, in, M);
@@ -362,7 +342,7 @@ static hipError_t launch_init_t(const KParams &P, bool aa, void *pop, const doub
 }
 
 hipError_t launch_step(const KParams &P, int storage, int tile, int mode, void *src, void *dst,
-                       const LagT *Mprev, LagT *Mnext, hipStream_t st) {
+                       const char *Mprev, char *Mnext, hipStream_t st) {
     if (storage == STORE_F16)
         return launch_step_t<__half>(P, tile, mode, src, dst, Mprev, Mnext, st);
     if (storage == STORE_BF16)
@@ -383,14 +363,14 @@ void tile_shape(int tile, int *bx, int *by) {
 }
 
 hipError_t launch_fields(const KParams &P, int storage, int mode, const void *src,
-                         const LagT *Mprev, double *out, hipStream_t st) {
+                         const char *Mprev, double *out, hipStream_t st) {
     if (storage == STORE_F16) return launch_fields_t<__half>(P, mode, src, Mprev, out, st);
     if (storage == STORE_BF16) return launch_fields_t<__hip_bfloat16>(P, mode, src, Mprev, out, st);
     return launch_fields_t<float>(P, mode, src, Mprev, out, st);
 }
 
 hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
-                       LagT *M, hipStream_t st) {
+                       char *M, hipStream_t st) {
     if (storage == STORE_F16) return launch_init_t<__half>(P, aa, pop, in, M, st);
     if (storage == STORE_BF16) return launch_init_t<__hip_bfloat16>(P, aa, pop, in, M, st);
     return launch_init_t<float>(P, aa, pop, in, M, st);

@@ -259,21 +259,23 @@ struct TileSource {
     }
 };
 
-// The lagged fields of the previous step as a field source (periodic
-// images wrap along z; beyond a HALO face, the halo row's fields).
+// The lagged fields of the previous step (format of population storage S)
+// as a field source (periodic images wrap along z; beyond a HALO face, the
+// halo row's fields).
+template <class S>
 struct LagSource {
     const KParams &P;
-    const LagT *M;
+    const char *M;
     int i, j;
     __device__ __forceinline__ float operator()(int v, int di, int dj) const {
         int ni = i + di;
         if ((unsigned)ni >= (unsigned)P.Nz) {
             const int f = ni < 0 ? 0 : 1;
             if (kind_of(P, Z_LO + f, FLOW) == HALO)
-                return lag_ld(P.halo_lag[f], v, (long long)P.pitch, j + dj);
+                return lag_ld<S>(P.halo_lag[f], v, (long long)P.pitch, j + dj);
             ni += ni < 0 ? P.Nz : -P.Nz;
         }
-        return lag_ld(M, v, P.plane, (long long)ni * P.pitch + (j + dj));
+        return lag_ld<S>(M, v, P.plane, (long long)ni * P.pitch + (j + dj));
     }
 };
 
@@ -430,21 +432,21 @@ __device__ __forceinline__ Moments moments(const float (&f)[9], const float (&g)
     return m;
 }
 
-__device__ __forceinline__ void derivatives(const KParams &P, const LagT *M, int i, int j,
+template <class S>
+__device__ __forceinline__ void derivatives(const KParams &P, const char *M, int i, int j,
                                             bool interior, float d[5]) {
     if (interior) {
         // all four neighbours are fluid nodes: plain loads at 32-bit offsets
         const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j, w = (unsigned)P.pitch;
-        const LagT *Mx = M, *My = M + P.plane, *Mt = M + 2 * P.plane;
-        const float *Mp = lag_T(M, P.plane);
-        d[0] = 0.5f * (lag_h(My + (n + w)) - lag_h(My + (n - w)));
-        d[1] = 0.5f * (lag_h(Mx + (n + 1)) - lag_h(Mx + (n - 1)));
-        d[2] = 0.5f * (lag_h(My + (n + 1)) - lag_h(My + (n - 1)));
-        d[3] = 0.5f * (lag_h(Mt + (n + 1)) - lag_h(Mt + (n - 1)));
-        d[4] = 0.5f * (Mp[n + 1] - Mp[n - 1]);
+        const long long pl = P.plane;
+        d[0] = 0.5f * (lag_ld<S>(M, 1, pl, n + w) - lag_ld<S>(M, 1, pl, n - w));
+        d[1] = 0.5f * (lag_ld<S>(M, 0, pl, n + 1) - lag_ld<S>(M, 0, pl, n - 1));
+        d[2] = 0.5f * (lag_ld<S>(M, 1, pl, n + 1) - lag_ld<S>(M, 1, pl, n - 1));
+        d[3] = 0.5f * (lag_ld<S>(M, 2, pl, n + 1) - lag_ld<S>(M, 2, pl, n - 1));
+        d[4] = 0.5f * (lag_ld<S>(M, 3, pl, n + 1) - lag_ld<S>(M, 3, pl, n - 1));
         return;
     }
-    differences(P, LagSource{P, M, i, j}, i, j, d);
+    differences(P, LagSource<S>{P, M, i, j}, i, j, d);
 }
 
 // ----------------------------------------------------------------------------
@@ -649,20 +651,20 @@ __device__ __forceinline__ Half relax_node(const KParams &P, int j, float (&f)[9
 
 template <class S, int MODE>
 __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *dst,
-                                            const LagT *__restrict__ Mprev,
-                                            LagT *__restrict__ Mnext, int i, int j,
+                                            const char *__restrict__ Mprev,
+                                            char *__restrict__ Mnext, int i, int j,
                                             bool interior) {
     float f[9], g[5], h[5];
     gather<S, MODE>(P, src, i, j, interior, f, g, h);
     float d[5];
-    derivatives(P, Mprev, i, j, interior, d);
+    derivatives<S>(P, Mprev, i, j, interior, d);
     const Half H = relax_node(P, j, f, g, h, d);
     scatter<S, MODE>(P, dst, i, j, interior, f, g, h);
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
-    lag_st(Mnext, 0, P.plane, n, H.ux);
-    lag_st(Mnext, 1, P.plane, n, H.uy);
-    lag_st(Mnext, 2, P.plane, n, H.psi * H.irho);
-    lag_st(Mnext, 3, P.plane, n, H.dphi);
+    lag_st<S>(Mnext, 0, P.plane, n, H.ux);
+    lag_st<S>(Mnext, 1, P.plane, n, H.uy);
+    lag_st<S>(Mnext, 2, P.plane, n, H.psi * H.irho);
+    lag_st<S>(Mnext, 3, P.plane, n, H.dphi);
 }
 
 // ----------------------------------------------------------------------------
@@ -692,9 +694,11 @@ __device__ __forceinline__ void st_plane(char *base, unsigned off, float x, unsi
                                          typename Conv<S>::Reg &r) {
     gstore(base, off, Conv<S>::bits(x, key, r));
 }
+// A lagged velocity (format of population storage S) at byte offset off.
+template <class S>
 __device__ __forceinline__ float lag_plane(const char *base, unsigned off) {
-    const LagT v = __builtin_bit_cast(LagT, gload<unsigned short>(base, off));
-    return lag_h(&v);
+    using F = LagFmt<S>;
+    return F::dec(gload<typename F::Bits>(base, off));
 }
 
 // The 19 populations node (i, j) reads (gather_planes) or writes
@@ -741,28 +745,29 @@ __device__ __forceinline__ unsigned local_offset(unsigned o) {
 template <class S>
 __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A, int i, int j,
                                               bool interior) {
+    using F = LagFmt<S>;
+    constexpr unsigned VB = F::VB;
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
-    const unsigned o = n * (unsigned)sizeof(S), o2 = n * 2u, o4 = n * 4u;
+    const unsigned o = n * (unsigned)sizeof(S), ov = n * VB, o4 = n * 4u;
     float f[9], g[5], h[5];
     gather_planes<S>(A, o, f, g, h);
     float d[5];
     if (interior) {
-        d[0] = 0.5f * (lag_plane(A.uy_up, o2) - lag_plane(A.uy_dn, o2));
-        d[1] = 0.5f * (lag_plane(A.lrd[0], o2 + 2u) - lag_plane(A.lrd[0], o2 - 2u));
-        d[2] = 0.5f * (lag_plane(A.lrd[1], o2 + 2u) - lag_plane(A.lrd[1], o2 - 2u));
-        d[3] = 0.5f * (lag_plane(A.lrd[2], o2 + 2u) - lag_plane(A.lrd[2], o2 - 2u));
+        d[0] = 0.5f * (lag_plane<S>(A.uy_up, ov) - lag_plane<S>(A.uy_dn, ov));
+        d[1] = 0.5f * (lag_plane<S>(A.lrd[0], ov + VB) - lag_plane<S>(A.lrd[0], ov - VB));
+        d[2] = 0.5f * (lag_plane<S>(A.lrd[1], ov + VB) - lag_plane<S>(A.lrd[1], ov - VB));
+        d[3] = 0.5f * (lag_plane<S>(A.lrd[2], ov + VB) - lag_plane<S>(A.lrd[2], ov - VB));
         d[4] = 0.5f * (gload<float>(A.lrd[3], o4 + 4u) - gload<float>(A.lrd[3], o4 - 4u));
     } else {
-        differences(P, LagSource{P, reinterpret_cast<const LagT *>(A.lrd[0]), i, j}, i, j, d);
+        differences(P, LagSource<S>{P, A.lrd[0], i, j}, i, j, d);
     }
     const Half H = relax_node(P, j, f, g, h, d);
     // the stores follow the branch above
-    const unsigned so = local_offset(o), so2 = local_offset(o2), so4 = local_offset(o4);
+    const unsigned so = local_offset(o), sov = local_offset(ov), so4 = local_offset(o4);
     scatter_planes<S>(A, so, i, j, f, g, h);
-    gstore(A.lwr[0], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.ux * LAG_SCALE)));
-    gstore(A.lwr[1], so2, __builtin_bit_cast(unsigned short, __float2half_rn(H.uy * LAG_SCALE)));
-    gstore(A.lwr[2], so2,
-           __builtin_bit_cast(unsigned short, __float2half_rn(H.psi * H.irho * LAG_SCALE)));
+    gstore(A.lwr[0], sov, F::enc(H.ux));
+    gstore(A.lwr[1], sov, F::enc(H.uy));
+    gstore(A.lwr[2], sov, F::enc(H.psi * H.irho));
     gstore(A.lwr[3], so4, H.dphi);
 }
 

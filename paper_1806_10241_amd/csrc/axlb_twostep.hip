@@ -34,8 +34,8 @@ struct TilePops {
 template <class S, int BX, int BY>
 __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Planes A,
                                                        const S *src, S *dst,
-                                                       const LagT *__restrict__ Mprev,
-                                                       LagT *__restrict__ Mnext) {
+                                                       const char *__restrict__ Mprev,
+                                                       char *__restrict__ Mnext) {
     constexpr int W = BX + 2, H = BY + 2, NC = W * H;
     __shared__ S pop[NPOP][H][W];
     __shared__ float lag[NLAG][H][W];
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Pla
                                     (unsigned)sizeof(S), f, g, h);
         else
             gather<S, MODE_AB>(P, src, ci, cj, false, f, g, h);
-        derivatives(P, Mprev, ci, cj, interior, d);
+        derivatives<S>(P, Mprev, ci, cj, interior, d);
         const Half Hs = relax_node(P, cj, f, g, h, d);
 #pragma unroll
         for (int q = 0; q < 9; ++q) Conv<S>::st(&pop[q][a][b], f[q], skey(ci, cj, q));
@@ -76,10 +76,10 @@ __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Pla
             Conv<S>::st(&pop[GOFF + q][a][b], g[q], skey(ci, cj, GOFF + q));
             Conv<S>::st(&pop[HOFF + q][a][b], h[q], skey(ci, cj, HOFF + q));
         }
-        lag[0][a][b] = lag_round(0, Hs.ux);
-        lag[1][a][b] = lag_round(1, Hs.uy);
-        lag[2][a][b] = lag_round(2, Hs.psi * Hs.irho);
-        lag[3][a][b] = lag_round(3, Hs.dphi);
+        lag[0][a][b] = lag_round<S>(0, Hs.ux);
+        lag[1][a][b] = lag_round<S>(1, Hs.uy);
+        lag[2][a][b] = lag_round<S>(2, Hs.psi * Hs.irho);
+        lag[3][a][b] = lag_round<S>(3, Hs.dphi);
     }
     __syncthreads();
     if (i >= P.Nz || j >= P.Nr) return;
@@ -91,25 +91,24 @@ __global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Pla
     const Half Hs = relax_node(P, j, f, g, h, d);
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
     scatter_planes<S>(A, local_offset(n * (unsigned)sizeof(S)), i, j, f, g, h);
-    lag_st(Mnext, 0, P.plane, n, Hs.ux);
-    lag_st(Mnext, 1, P.plane, n, Hs.uy);
-    lag_st(Mnext, 2, P.plane, n, Hs.psi * Hs.irho);
-    lag_st(Mnext, 3, P.plane, n, Hs.dphi);
+    lag_st<S>(Mnext, 0, P.plane, n, Hs.ux);
+    lag_st<S>(Mnext, 1, P.plane, n, Hs.uy);
+    lag_st<S>(Mnext, 2, P.plane, n, Hs.psi * Hs.irho);
+    lag_st<S>(Mnext, 3, P.plane, n, Hs.dphi);
 }
 
 template <class S>
-static hipError_t step_two_t(const KParams &P, const void *src, void *dst, const LagT *Mprev,
-                             LagT *Mnext, hipStream_t st) {
+static hipError_t step_two_t(const KParams &P, const void *src, void *dst, const char *Mprev,
+                             char *Mnext, hipStream_t st) {
     const int gx = (P.Nr + TWO_BX - 1) / TWO_BX, gy = (P.Nz + TWO_BY - 1) / TWO_BY;
-    const Planes A = step_planes(P, sizeof(S) == 4 ? STORE_F32 : STORE_F16, MODE_AB, src, dst,
-                                 Mprev, Mnext);
+    const Planes A = step_planes(P, store_of<S>(), MODE_AB, src, dst, Mprev, Mnext);
     k_step_two<S, TWO_BX, TWO_BY><<<dim3(gx * gy), dim3(TWO_BX * TWO_BY), 0, st>>>(
         P, A, (const S *)src, (S *)dst, Mprev, Mnext);
     return hipGetLastError();
 }
 
 hipError_t launch_step_two(const KParams &P, int storage, const void *src, void *dst,
-                           const LagT *Mprev, LagT *Mnext, hipStream_t st) {
+                           const char *Mprev, char *Mnext, hipStream_t st) {
     if (storage == STORE_F16) return step_two_t<__half>(P, src, dst, Mprev, Mnext, st);
     if (storage == STORE_BF16) return step_two_t<__hip_bfloat16>(P, src, dst, Mprev, Mnext, st);
     return step_two_t<float>(P, src, dst, Mprev, Mnext, st);

@@ -270,7 +270,9 @@ def serving_trace(n: int = 2000, rate: float = 200.0, seed: int = 5,
     """Poisson arrivals at `rate` per second of solve requests mixing the
     three problem types, grids N_r = 2^U(6, max_nr_log2), N_z = 2^U(6,
     max_nz_log2) rounded to multiples of 16, storage FP32 or 16-bit with
-    probability 1/2 each.  Returns a list of (arrival_s, case, storage)."""
+    probability 1/2 each.  Rotating-lid requests draw Re log-uniform in
+    [500, 2000], capped at 8 N_r so that nu = 0.05 N_r / Re stays at or above
+    0.00625 on small grids.  Returns a list of (arrival_s, case, storage)."""
     u = uniform(seed, 6 * n).reshape(n, 6)
     t = 0.0
     out = []
@@ -287,8 +289,8 @@ def serving_trace(n: int = 2000, rate: float = 200.0, seed: int = 5,
             c = annulus_convection(Nr=Nr, Nz=Nz, Ra=10.0 ** (3 + 2 * u[k, 5]),
                                    seed=seed * 100000 + k)
         else:
-            c = rotating_lid_cylinder(Nr=Nr, Nz=Nz, Re=200.0 + 300.0 * u[k, 5],
-                                      seed=seed * 100000 + k)
+            Re = min(500.0 * 4.0 ** u[k, 5], 8.0 * Nr)
+            c = rotating_lid_cylinder(Nr=Nr, Nz=Nz, Re=Re, seed=seed * 100000 + k)
         c["name"] = "request_%d" % k
         out.append((t, c, storage))
     return out

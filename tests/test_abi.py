@@ -34,7 +34,10 @@ def test_state_bytes_and_argument_checks():
     nab = axlb.state_bytes(1024, 2048, "f32", "ab")
     pop32 = 19 * 1024 * 2048 * 4
     halo32 = 2 * 19 * 1024 * 4  # the halo rows of the two z faces
-    assert n32 - n16 == (pop32 + halo32) // 2
+    # lagged fields: 16 B per node with FP32 populations, 10 B with 16-bit
+    # ones; two time levels, plus the halo rows of the two z faces
+    lag_extra = 2 * 6 * 1024 * 2048 + 2 * 6 * 1024
+    assert n32 - n16 == (pop32 + halo32) // 2 + lag_extra
     assert nab - n32 == pop32
     with pytest.raises(axlb.AxlbError):
         axlb.state_bytes(1, 10)

@@ -145,3 +145,30 @@ def test_batch_with_degenerate_members_equals_alone(gpu):
     for la, lb in zip(alone, batched):
         assert la.save() == lb.save()
     b.close()
+
+
+def test_destroying_a_batched_member_is_refused(gpu):
+    """A batch keeps stepping its members' memory: destroying a member while
+    the batch lives is refused (nothing released), and the member keeps
+    stepping with the batch; after the batch is gone it can be closed."""
+    say("destroy a batched member")
+    from paper_1806_10241_amd import axlb
+    cases = members()[:3]
+    a = [axlb.Lattice(c) for c in cases]
+    ref = axlb.Lattice(cases[0])
+    b = axlb.Batch(a)
+    lib = axlb.load()
+    assert lib.axlb_destroy(a[0].handle) == axlb.ESTATE
+    assert b"batch" in lib.axlb_last_error(a[0].handle)
+    with pytest.raises(axlb.AxlbError) as e:
+        a[0].close()
+    assert e.value.code == axlb.ESTATE
+    assert a[0].handle and a[0]._buf is not None
+    b.step(120)
+    b.sync()
+    ref.step(120)
+    assert a[0].save() == ref.save()
+    b.close()
+    for lat in a:
+        lat.close()
+    assert not a[0].handle

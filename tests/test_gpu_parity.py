@@ -5,12 +5,15 @@ Metric: relative L2 error after 1000 steps of rho and T against their own
 norms, of each velocity component against the norm of the speed field
 |u| = (u_r^2 + u_z^2 + u_theta^2)^(1/2), and of rho - 1 against its own norm.
 Bars: 1e-5 with FP32 storage (rho - 1: 2e-4, the FP32 storage round-off
-bound); 2e-3 with binary16 storage (stochastic rounding); bfloat16 storage
-keeps 8 significant bits and is held to 1e-2 (Nusselt 2%), a measured bound
-that misses the 2e-3 goal.  A field whose oracle norm is zero must stay below
-1e-12.  Nusselt numbers within 0.5%.  The single-buffer (AA) and two-buffer (AB)
-layouts must agree bit for bit in FP32.  Sizes span several 64 x 4 tiles
-with ragged tails.
+bound); 2e-3 with 16-bit storage (binary16 and bfloat16, stochastic
+rounding).  bfloat16 keeps 8 significant bits and misses that bar: its tests
+are expected failures that report the measured error.  A field whose oracle
+norm is zero must stay below 1e-12.  Nusselt numbers within 0.5%.  Besides
+the L2 norms, the largest error at any single node is bounded (MAX_FACTOR
+times the L2 bar, against the largest value of the same scale), so that an
+error confined to a few edge nodes cannot hide in a large lattice.  The
+single-buffer (AA) and two-buffer (AB) layouts must agree bit for bit in
+FP32.  Sizes span several 64 x 4 tiles with ragged tails.
 """
 import numpy as np
 import pytest
@@ -21,13 +24,19 @@ from paper_1806_10241_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 FIELDS = ("rho", "ur", "uz", "uth", "T")
-TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 1e-2}
+TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-3}
+NU_TOL = 5e-3
+# per-node bar: MAX_FACTOR * (L2 bar) * (largest value of the field's scale)
+MAX_FACTOR = 30.0
+BF16_XFAIL = pytest.mark.xfail(
+    strict=False, reason="bfloat16 storage keeps 8 significant bits: measured field errors "
+    "2e-3 to 4e-3 and Nusselt errors up to 2% after 1000 steps, above the 2e-3 / 0.5% bars")
 # rho - 1 is a small difference of O(1) numbers: rounding every stored
 # population to FP32 (relative 2^-24) random-walks the density by about
 # 3 * 2^-24 * |f - w| per step, which after 1000 steps reaches ~1e-4 of
 # ||rho - 1|| in a weakly driven flow (measured 6e-5 by rounding the FP64
 # oracle's own state to FP32 every step).
-TOL_DRHO = {"f32": 2e-4, "f16": 2e-2, "bf16": 1.5e-1}
+TOL_DRHO = {"f32": 2e-4, "f16": 2e-2, "bf16": 2e-2}
 
 
 def field_errors(a, b):
@@ -45,6 +54,21 @@ def field_errors(a, b):
     return out
 
 
+def max_errors(a, b):
+    """Largest error at any node, relative to the largest value of the same
+    scale (the speed for velocity components, |T| for T, |rho - 1| for rho)."""
+    speed = np.sqrt(b["ur"] ** 2 + b["uz"] ** 2 + b["uth"] ** 2).max()
+    out = {}
+    for k in ("ur", "uz", "uth", "T"):
+        ref = speed if k != "T" else np.abs(b["T"]).max()
+        if ref > 0:
+            out[k] = float(np.abs(a[k] - b[k]).max() / ref)
+    dr = np.abs(b["rho"] - 1.0).max()
+    if dr > 0:
+        out["rho-1"] = float(np.abs(a["rho"] - b["rho"]).max() / dr)
+    return out
+
+
 def assert_parity(a, b, tol, label, tol_drho=None):
     for k, (err, norm) in field_errors(a, b).items():
         bar = tol_drho if k == "rho-1" else tol
@@ -54,6 +78,10 @@ def assert_parity(a, b, tol, label, tol_drho=None):
             assert err <= 1e-12, (label, k, err)
         else:
             assert err <= bar, (label, k, err)
+    for k, err in max_errors(a, b).items():
+        bar = tol_drho if k == "rho-1" else tol
+        if bar is not None:
+            assert err <= MAX_FACTOR * bar, (label, "max", k, err)
 
 
 def c1_case():
@@ -68,7 +96,37 @@ def c3_case():
     return I.rotating_lid_cylinder(Nr=70, Nz=140, Re=500.0, Ri=0.5, seed=13)
 
 
-CASES = {"c1": c1_case, "c2": c2_case, "c3": c3_case}
+def _developed(c, seed, T_init):
+    """Starts a case from a smooth flow with velocities of a few hundredths
+    instead of rest.  A Rayleigh-Benard cell at rest is a linearly unstable
+    state: the growing mode amplifies any difference between FP32 and FP64
+    rounding along with the seeded noise, so the early transient from rest is
+    no test of parity; a developed flow is."""
+    def fields():
+        F = smooth_fields(c["Nz"], c["Nr"], seed)
+        F["T"] = T_init + (F["T"] - 0.5)
+        return F
+    c["fields"] = fields
+    return c
+
+
+def rb_cold_case():
+    """Rayleigh-Benard convection in a cylinder (Section 3.3), cold fluid."""
+    return _developed(I.rayleigh_benard_cylinder(Nr=48, Nz=48, T_init=0.0, seed=21), 21, 0.0)
+
+
+def rb_hot_case():
+    return _developed(I.rayleigh_benard_cylinder(Nr=48, Nz=48, T_init=1.0, seed=22), 22, 1.0)
+
+
+def mixed_case():
+    """Mixed convection in a slender annulus with a turning inner cylinder
+    (Section 3.5), sigma = 0.05."""
+    return I.mixed_convection_annulus(Nr=16, sigma=0.05, seed=23)
+
+
+CASES = {"c1": c1_case, "c2": c2_case, "c3": c3_case, "rb_cold": rb_cold_case,
+         "rb_hot": rb_hot_case, "mixed": mixed_case}
 STEPS = 1000
 
 
@@ -95,34 +153,45 @@ def run_gpu(case, storage, layout, steps=STEPS):
     return lat, F
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "rb_cold", "rb_hot", "mixed"])
 @pytest.mark.parametrize("layout", ["aa", "ab"])
 def test_fp32_parity(gpu, oracle_runs, name, layout):
     say("parity f32", name, layout)
     ref, nu_ref = oracle_runs(name)
     lat, F = run_gpu(CASES[name](), "f32", layout)
     errs = field_errors(F, ref)
-    say("  errors", {k: "%.2e" % v[0] for k, v in errs.items()})
+    say("  errors", {k: "%.2e" % v[0] for k, v in errs.items()},
+        "max", {k: "%.2e" % v for k, v in max_errors(F, ref).items()})
     assert_parity(F, ref, TOL["f32"], (name, layout), TOL_DRHO["f32"])
     if nu_ref is not None:
         nu = lat.nusselt()
         for x, y in zip(nu, nu_ref):
-            assert abs(x - y) <= 5e-3 * abs(y), (nu, nu_ref)
+            assert abs(x - y) <= NU_TOL * abs(y), (nu, nu_ref)
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
-@pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_16bit_storage_parity(gpu, oracle_runs, name, storage):
+def _16bit_parity(oracle_runs, name, storage):
     say("parity", storage, name)
     ref, nu_ref = oracle_runs(name)
     lat, F = run_gpu(CASES[name](), storage, "aa")
     errs = field_errors(F, ref)
-    say("  errors", {k: "%.2e" % v[0] for k, v in errs.items()})
-    assert_parity(F, ref, TOL[storage], (name, storage), TOL_DRHO[storage])
     nu = lat.nusselt()
-    nu_tol = 5e-3 if storage == "f16" else 2e-2
+    say("  errors", {k: "%.2e" % v[0] for k, v in errs.items()},
+        "max", {k: "%.2e" % v for k, v in max_errors(F, ref).items()},
+        "Nu", ["%.2e" % (abs(x - y) / abs(y)) for x, y in zip(nu, nu_ref)])
+    assert_parity(F, ref, TOL[storage], (name, storage), TOL_DRHO[storage])
     for x, y in zip(nu, nu_ref):
-        assert abs(x - y) <= nu_tol * abs(y), (nu, nu_ref)
+        assert abs(x - y) <= NU_TOL * abs(y), (nu, nu_ref)
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_f16_storage_parity(gpu, oracle_runs, name):
+    _16bit_parity(oracle_runs, name, "f16")
+
+
+@BF16_XFAIL
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_bf16_storage_parity(gpu, oracle_runs, name):
+    _16bit_parity(oracle_runs, name, "bf16")
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3"])
@@ -146,6 +215,26 @@ def test_graph_bundles_equal_single_launches(gpu):
     b = axlb.Lattice(c)
     for _ in range(250):
         b.step(1)
+    assert a.save() == b.save()
+
+
+@pytest.mark.parametrize("layout", ["aa", "ab", "ab2"])
+def test_graph_tails_equal_single_launches(gpu, layout):
+    """Step counts that are not whole bundles replay a graph of the tail
+    (captured ahead by prepare_steps, or at first use); odd tails flip the
+    AA phase and, in the two-step layout, end with a single step.  The
+    state must equal one launch per step."""
+    say("graph tails", layout)
+    from paper_1806_10241_amd import axlb
+    c = c3_case()
+    a = axlb.Lattice(c, layout=layout)
+    a.prepare_steps(37)
+    for n in (37, 137, 2, 20, 1, 99):
+        a.step(n)
+    b = axlb.Lattice(c, layout=layout)
+    for _ in range(37 + 137 + 2 + 20 + 1 + 99):
+        b.step(1)
+    assert a.steps == b.steps
     assert a.save() == b.save()
 
 
@@ -204,6 +293,64 @@ def test_full_size_parity_in_bench_configuration(gpu, orc):
     for k in FIELDS:
         dg, dr = F[k] - f0_gpu[k], R[k] - f0_ref[k]
         assert np.linalg.norm(dg - dr) <= 1e-3 * np.linalg.norm(dr), k
+
+
+def test_full_size_parity_over_a_graph_bundle(gpu, orc):
+    """The benchmark workload at 1024 x 2048 from its own seeded initial
+    state, 100 steps (one captured graph bundle, autotuned tile) against the
+    oracle on every node."""
+    say("full size 1024x2048, 100 steps")
+    from paper_1806_10241_amd import axlb
+    c = I.rotating_lid_cylinder(Nr=1024, Nz=2048, Re=1000.0, Ri=0.5, u_noise=1e-4)
+    lat = axlb.Lattice(c)
+    lat.autotune(steps_per_trial=4)
+    lat.step(100)
+    ref = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
+    ref.step(100)
+    F, R = lat.fields(), ref.fields()
+    say("  errors", {k: "%.2e" % v[0] for k, v in field_errors(F, R).items()},
+        "max", {k: "%.2e" % v for k, v in max_errors(F, R).items()})
+    assert_parity(F, R, TOL["f32"], "t=100", TOL_DRHO["f32"])
+
+
+@pytest.mark.parametrize("kind", ["annulus", "lid"])
+def test_fp32_parity_at_1024_rows(gpu, orc, kind):
+    """1000 steps of a lattice 1024 nodes wide and 32 high: a periodic
+    annulus with a fast-turning inner wall and axial flow, or a short
+    cylinder under a rotating lid, where the radial differences of the
+    lagged velocities are smallest relative to the values."""
+    say("parity f32 at 1024 rows", kind)
+    from paper_1806_10241_amd import axlb
+    if kind == "annulus":
+        c = I.couette_poiseuille_conduction(Nr=1024, Nz=32, r_inner=512.0, u_wall=0.05,
+                                            g=1e-6, nu=0.05, alpha=0.05)
+    else:
+        c = I.rotating_lid_cylinder(Nr=1024, Nz=32, Re=1000.0, Ri=0.5, seed=31)
+    ref = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
+    ref.step(STEPS)
+    lat = axlb.Lattice(c)
+    lat.step(STEPS)
+    F, R = lat.fields(), ref.fields()
+    say("  errors", {k: "%.2e" % v[0] for k, v in field_errors(F, R).items()},
+        "max", {k: "%.2e" % v for k, v in max_errors(F, R).items()})
+    assert_parity(F, R, TOL["f32"], kind, TOL_DRHO["f32"])
+
+
+def test_residual_matches_the_oracle_definition(gpu, orc):
+    """axlb_residual over K steps equals the oracle's residual of the same
+    two field snapshots (the fields the device reduces, copied out)."""
+    say("residual vs oracle definition")
+    from paper_1806_10241_amd import axlb
+    for c, K in ((c2_case(), 100), (c3_case(), 37), (c1_case(), 250)):
+        lat = axlb.Lattice(c)
+        lat.step(50)
+        assert lat.residual() == float("inf")
+        F0 = lat.fields()
+        lat.step(K)
+        F1 = lat.fields()
+        r = lat.residual()
+        want = orc.residual(F1, F0, K)
+        assert r == pytest.approx(want, rel=1e-12), (c["name"], r, want)
 
 
 def test_full_size_bench_launches_equal_checked_launches(gpu):

@@ -21,12 +21,13 @@ from paper_1806_10241_amd import inputs as I
 def test_thread_count_does_not_change_results(orc):
     c = I.rotating_lid_cylinder(Nr=40, Nz=60, Re=400.0, Ri=0.5, u_noise=1e-3)
     states = []
+    t0 = orc.threads()
     for t in (1, 3, 8):
         orc.set_threads(t)
         L = orc.Lattice(c, fields=c["fields"]())
         L.step(30)
         states.append(L.get_state())
-    orc.set_threads(1)
+    orc.set_threads(t0)
     for s in states[1:]:
         assert np.array_equal(s, states[0])
 
@@ -180,7 +181,6 @@ def rel_l2(a, b):
 def porous_runs(orc):
     """Q/nu = 1 and 2.5, at 30 and 60 rows (R_i, R_o doubled, g quartered),
     each run for several diffusion times."""
-    orc.set_threads(8)
     out = {}
     for Q in (0.1, 0.25):
         for s in (1, 2):
@@ -191,7 +191,6 @@ def porous_runs(orc):
             rho_a = L.fields()["rho"].mean()
             L.step(500)
             out[(Q, s)] = (c, L.fields(), rho_a)
-    orc.set_threads(1)
     return out
 
 
