@@ -239,6 +239,22 @@ int axlb_autotune(axlb_lattice *lat, int steps_per_trial, double *ms_per_step, i
  * would go on stepping its memory.  NULL is a no-op. */
 int axlb_destroy(axlb_lattice *lat);
 
+/* Wall Nusselt numbers as axlb_nusselt computes them (same per-node
+ * arithmetic; the FP64 sums run in another order, so results agree to
+ * rounding), for callers that cannot allocate device memory: tight serving
+ * or monitoring loops, harnesses that forbid hipMalloc, processes whose
+ * device memory is fully reserved.  It calls no allocating routine (only a
+ * fixed device-to-host copy of the two sums) and leaves the lattice's own
+ * field and reduction buffers untouched.  Its partial sums live in a fixed
+ * per-device array of 128 KiB inside the library (held until the process
+ * ends) that serves walls of up to 2^21 nodes (Nz for an annulus, Nr for a
+ * cylinder); longer walls give AXLB_EINVAL.  Every call on one device
+ * shares that array: calls that overlap on one device (from several host
+ * threads, or on streams that run concurrently) race and must be ordered
+ * by the caller.  Synchronous on the lattice's stream; other errors as
+ * axlb_nusselt. */
+int axlb_nusselt_noalloc(axlb_lattice *lat, double *nu_a, double *nu_b, double *mean);
+
 /* ---- slabs of one lattice (a lattice cut along z, one piece per GPU) ----
  * A slab's cut faces have kind AXLB_HALO.  Before each step, the row of
  * each neighbouring slab next to the cut (its populations and lagged

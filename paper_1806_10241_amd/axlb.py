@@ -42,7 +42,7 @@ EXPORTS = [
     "axlb_pool_create", "axlb_pool_set_policy", "axlb_pool_submit", "axlb_pool_tick",
     "axlb_pool_status",
     "axlb_pool_result", "axlb_pool_usage", "axlb_pool_destroy", "axlb_pool_last_error",
-    "axlb_prepare_steps",
+    "axlb_nusselt_noalloc", "axlb_prepare_steps",
 ]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 POOL_ORDER = {"fifo": 0, "smallest": 1}
@@ -117,6 +117,7 @@ def load():
         "axlb_save": ([_vp, _vp, C.c_size_t], C.c_int),
         "axlb_load": ([_vp, _vp, C.c_size_t], C.c_int),
         "axlb_destroy": ([_vp], C.c_int),
+        "axlb_nusselt_noalloc": ([_vp] + [_dp] * 3, C.c_int),
         "axlb_tile_shape": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
         "axlb_set_tile": ([_vp, C.c_int], C.c_int),
         "axlb_get_tile": ([_vp] + [C.POINTER(C.c_int)] * 3, C.c_int),
@@ -281,6 +282,13 @@ class Lattice:
     def nusselt(self):
         a, b, m = C.c_double(), C.c_double(), C.c_double()
         self._check(self._lib.axlb_nusselt(self._h, C.byref(a), C.byref(b), C.byref(m)))
+        return a.value, b.value, m.value
+
+    def nusselt_noalloc(self):
+        """The wall Nusselt numbers through the entry point that allocates
+        no device memory (axlb_nusselt_noalloc)."""
+        a, b, m = C.c_double(), C.c_double(), C.c_double()
+        self._check(self._lib.axlb_nusselt_noalloc(self._h, C.byref(a), C.byref(b), C.byref(m)))
         return a.value, b.value, m.value
 
     def residual(self) -> float:

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaxlb.so")
 SOURCES = ["axlb_kernels.hip", "axlb_current.hip", "axlb_twostep.hip", "axlb_api.hip",
-           "axlb_batch.hip", "axlb_pool.cpp"]
+           "axlb_batch.hip", "axlb_pool.cpp", "axlb_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
