@@ -103,6 +103,14 @@ extern "C" {
 #define AXLB_HALO 6      /* z faces only, all fields, AXLB_LAYOUT_AB with lagged derivatives:
                             the neighbours beyond the face are the boundary row of an
                             adjacent slab, imported with axlb_halo_import (below)        */
+#define AXLB_VELOCITY 7  /* f only: a wall through which the fluid crosses with the imposed
+                            normal velocity `value` (along +r on r faces, +z on z faces):
+                            an inlet or outlet; tangential velocity 0.  Moving-wall
+                            bounce-back with rho_0 = 1, so the wall carries the mass flux
+                            `value` per unit area.  g on such a face must impose u_theta
+                            (NOSLIP, DIRICHLET, OMEGA_R) and h must impose T (DIRICHLET);
+                            their anti-bounce-back adds the advective part u_n^2 s_w.  No
+                            case of the paper uses one                                  */
 
 typedef struct axlb_lattice axlb_lattice;
 

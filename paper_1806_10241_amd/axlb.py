@@ -23,7 +23,7 @@ LAYOUT_AA, LAYOUT_AB, LAYOUT_AB2 = 0, 1, 2
 ANNULUS, CYLINDER = 0, 1
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
-NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, HALO = 0, 1, 2, 3, 4, 5, 6
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, HALO, VELOCITY = 0, 1, 2, 3, 4, 5, 6, 7
 
 STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
 LAYOUT = {"aa": LAYOUT_AA, "ab": LAYOUT_AB, "ab2": LAYOUT_AB2}

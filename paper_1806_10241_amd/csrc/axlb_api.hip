@@ -58,7 +58,8 @@ static int fail(axlb_lattice *lat, int code, const std::string &msg) {
 }
 
 static bool is_wall(int k) {
-    return k == AXLB_NOSLIP || k == AXLB_DIRICHLET || k == AXLB_OMEGA_R || k == AXLB_ADIABATIC;
+    return k == AXLB_NOSLIP || k == AXLB_DIRICHLET || k == AXLB_OMEGA_R || k == AXLB_ADIABATIC ||
+           k == AXLB_VELOCITY;
 }
 
 static bool rate_ok(double w) { return std::isfinite(w) && w > 0.0 && w < 2.0; }
@@ -127,6 +128,11 @@ static int check_bcs(axlb_lattice *L) {
                             "a face must be a wall, periodic, a halo or the axis for all three fields");
         }
     }
+    for (int f = 0; f < 4; ++f)
+        if (L->kind[f][0] == AXLB_VELOCITY &&
+            (L->kind[f][1] == AXLB_ADIABATIC || L->kind[f][2] != AXLB_DIRICHLET))
+            return fail(L, AXLB_EINVAL,
+                        "a VELOCITY face needs imposed u_theta (g) and imposed T (h)");
     if (halo && (L->layout != AXLB_LAYOUT_AB || L->deriv != AXLB_DERIV_LAGGED))
         return fail(L, AXLB_EINVAL, "HALO faces need the two-buffer, one-step layout");
     return AXLB_OK;
@@ -403,7 +409,7 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
 int axlb_set_bc(axlb_lattice *L, int face, int field, int kind, double value) {
     if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
     if (L->started) return fail(L, AXLB_ESTATE, "boundary rules are fixed once stepping started");
-    if (face < 0 || face > 3 || field < 0 || field > 2 || kind < 0 || kind > 6)
+    if (face < 0 || face > 3 || field < 0 || field > 2 || kind < 0 || kind > 7)
         return fail(L, AXLB_EINVAL, "face, field or kind out of range");
     if (L->cylinder && face == AXLB_R_IN && kind != AXLB_MIRROR)
         return fail(L, AXLB_EINVAL, "the inner face of a cylinder is the axis");
@@ -412,7 +418,11 @@ int axlb_set_bc(axlb_lattice *L, int face, int field, int kind, double value) {
     if ((kind == AXLB_PERIODIC || kind == AXLB_HALO) && face != AXLB_Z_LO && face != AXLB_Z_HI)
         return fail(L, AXLB_EINVAL, "PERIODIC and HALO are only for z faces");
     if (field == AXLB_FLOW && (kind == AXLB_DIRICHLET || kind == AXLB_OMEGA_R || kind == AXLB_ADIABATIC))
-        return fail(L, AXLB_EINVAL, "FLOW walls are NOSLIP");
+        return fail(L, AXLB_EINVAL, "FLOW walls are NOSLIP or VELOCITY");
+    if (field != AXLB_FLOW && kind == AXLB_VELOCITY)
+        return fail(L, AXLB_EINVAL, "VELOCITY is a rule for f (FLOW) only");
+    if (kind == AXLB_VELOCITY && !std::isfinite(value))
+        return fail(L, AXLB_EINVAL, "VELOCITY value must be finite");
     if (field == AXLB_THERMAL && (kind == AXLB_NOSLIP || kind == AXLB_OMEGA_R))
         return fail(L, AXLB_EINVAL, "THERMAL walls are DIRICHLET or ADIABATIC");
     if (kind == AXLB_DIRICHLET && !std::isfinite(value))

@@ -11,7 +11,10 @@ namespace axlb {
 // Faces, distributions and boundary kinds (numbering of include/axlb.h).
 enum { R_IN = 0, R_OUT = 1, Z_LO = 2, Z_HI = 3 };
 enum { FLOW = 0, SWIRL = 1, THERMAL = 2 };
-enum { NOSLIP = 0, PERIODIC = 1, MIRROR = 2, DIRICHLET = 3, OMEGA_R = 4, ADIABATIC = 5, HALO = 6 };
+enum {
+    NOSLIP = 0, PERIODIC = 1, MIRROR = 2, DIRICHLET = 3, OMEGA_R = 4, ADIABATIC = 5, HALO = 6,
+    VELOCITY = 7
+};
 
 // Plane numbering of the population buffer: f_0..f_8, g_0..g_4, h_0..h_4.
 constexpr int NPOP = 19;

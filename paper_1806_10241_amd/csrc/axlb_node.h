@@ -50,7 +50,35 @@ __device__ __forceinline__ unsigned skey(int i, int j, int q) {
 }
 
 __device__ __forceinline__ bool is_wall(int k) {
-    return k == NOSLIP || k == DIRICHLET || k == OMEGA_R || k == ADIABATIC;
+    return k == NOSLIP || k == DIRICHLET || k == OMEGA_R || k == ADIABATIC || k == VELOCITY;
+}
+
+// Normal velocity that a face imposes (VELOCITY for f: along +y on radial
+// faces, +x on axial faces), 0 for every other kind.
+__device__ __forceinline__ float face_velocity(const KParams &P, int face) {
+    return kind_of(P, face, FLOW) == VELOCITY ? val_of<FLOW>(P, face) : 0.f;
+}
+
+// Moving-wall bounce-back for f: the population q that comes back off a
+// wall moving with u_w along the face normal gains 2 w_q rho_0 (e_q . u_w) /
+// c_s^2 = 6 w_q (e_q . u_w) with rho_0 = 1 (shifted storage subtracts the
+// same w_q on both sides).  Lattice weights 4/9, 1/9, 1/36.
+template <int Q>
+__device__ __forceinline__ float moving_wall(const KParams &P, int face) {
+    using L = Lat<FLOW>;
+    constexpr int ex = L::ex(Q), ey = L::ey(Q);
+    constexpr float w = (ex == 0 && ey == 0) ? 4.f / 9.f : ((ex == 0 || ey == 0) ? 1.f / 9.f : 1.f / 36.f);
+    const float e_n = (float)(face <= R_OUT ? ey : ex);
+    return 6.f * w * e_n * val_of<FLOW>(P, face);
+}
+
+// Unshifted wall value of g or h (u_theta,w or T_w) for the advective part
+// of the anti-bounce-back at a wall the fluid crosses.
+template <int FLD>
+__device__ __forceinline__ float wall_raw(const KParams &P, int face, float ym) {
+    const int k = kind_of(P, face, FLD);
+    const float v = val_of<FLD>(P, face);
+    return k == DIRICHLET ? v : (k == OMEGA_R ? v * ym : 0.f);
 }
 
 // Value that the advection-diffusion wall rule imposes (psi_w = u_theta,w
@@ -109,9 +137,14 @@ __device__ __forceinline__ float pull_edge(const KParams &P, const Src &src, int
         // it into plane Q.
         constexpr int slot = AA ? Q : L::opp(Q);
         const float v = src(L::OFF + slot, i, j);
-        if (FLD == FLOW || kind_of(P, wall, FLD) == ADIABATIC) return v;
+        const bool moving = kind_of(P, wall, FLOW) == VELOCITY;
+        if (FLD == FLOW) return moving ? v + moving_wall<Q>(P, wall) : v;
+        if (kind_of(P, wall, FLD) == ADIABATIC) return v;
         const float ym = P.r0 + (float)j + 0.5f - 0.5f * (float)ey;
-        return -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
+        const float r = -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
+        if (!moving) return r;
+        const float un = val_of<FLOW>(P, wall);
+        return r + un * un * wall_raw<FLD>(P, wall, ym);
     }
     float sign = 1.f;
     int qs = Q;
@@ -176,10 +209,18 @@ __device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, 
     if (fy >= 0 && is_wall(kind_of(P, fy, FLD))) wall = fy;
     else if (fx >= 0 && is_wall(kind_of(P, fx, FLD))) wall = fx;
     if (wall >= 0) {
+        // it comes back to (i, j) as population opp Q
         float w = v;
-        if (FLD != FLOW && kind_of(P, wall, FLD) != ADIABATIC) {
+        const bool moving = kind_of(P, wall, FLOW) == VELOCITY;
+        if (FLD == FLOW) {
+            if (moving) w = v + moving_wall<L::opp(Q)>(P, wall);
+        } else if (kind_of(P, wall, FLD) != ADIABATIC) {
             const float ym = P.r0 + (float)j + 0.5f + 0.5f * (float)ey;
             w = -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
+            if (moving) {
+                const float un = val_of<FLOW>(P, wall);
+                w = w + un * un * wall_raw<FLD>(P, wall, ym);
+            }
         }
         Conv<S>::st(A + (L::OFF + L::opp(Q)) * P.plane + (long long)i * P.pitch + j, w,
                     skey(i, j, L::OFF + Q));
@@ -230,7 +271,11 @@ __device__ __forceinline__ float field_at(const KParams &P, const Get &get, int 
     const float q1 = get(v, 0, 0);
     if (k == MIRROR) return (v == 0 || v == 3) ? q1 : -q1;
     if (k == ADIABATIC) return q1;
-    if (v <= 1) return -q1;
+    if (v <= 1) {
+        // the velocity component normal to a wall that imposes one: 2 u_w - q
+        const int normal = face <= R_OUT ? 1 : 0;
+        return v == normal ? 2.f * face_velocity(P, face) - q1 : -q1;
+    }
     const float yw = P.r0 + (float)j + 0.5f + 0.5f * (float)dj;
     const float s = v == 2 ? wall_value<SWIRL>(P, face, yw) : wall_value<THERMAL>(P, face, yw);
     return 2.f * s - q1;

@@ -150,6 +150,28 @@ def porous_annulus(Nr: int = 30, Nz: int = 4, r_inner: float = 10.0, Q: float = 
                 T_ref=0.5, Q=Q, fields=lambda: {"T": np.full((Nz, Nr), 0.5)})
 
 
+def pipe_throughflow(Nr: int = 24, Nz: int = 48, U: float = 0.01, nu: float = 0.05,
+                     alpha: float = 0.05, u_wall: float = 0.0, seed: int = 8) -> dict:
+    """Flow through a circular pipe (cylinder, axis by the mirror rule): a
+    uniform axial velocity U enters through the bottom face and leaves
+    through the top face (imposed-velocity faces), the side wall is at rest
+    (or turns with u_theta = u_wall) and held at T = 0 while the inflow
+    carries T = 1 and the outflow face is held at T = 0.  Starts at rest at
+    T = 0 plus seeded noise of amplitude 1e-4."""
+    bc = {}
+    _axis(bc)
+    _walls(bc, R_OUT, (DIRICHLET, u_wall), (DIRICHLET, 0.0))
+    bc[(Z_LO, FLOW)] = (VELOCITY, U)
+    bc[(Z_LO, SWIRL)] = (NOSLIP, 0.0)
+    bc[(Z_LO, THERMAL)] = (DIRICHLET, 1.0)
+    bc[(Z_HI, FLOW)] = (VELOCITY, U)
+    bc[(Z_HI, SWIRL)] = (NOSLIP, 0.0)
+    bc[(Z_HI, THERMAL)] = (DIRICHLET, 0.0)
+    return dict(name="pipe_throughflow", Nr=Nr, Nz=Nz, cylinder=1, r_inner=0.0, nu=nu,
+                alpha=alpha, Pr=nu / alpha, Ra=0.0, g_axial=0.0, T0=0.5, omega3=1.0, bc=bc,
+                T_ref=0.5, U=U, seed=seed, fields=_perturbed_T(seed, Nz, Nr, base=0.0))
+
+
 def annulus_convection(Nr: int = 256, Nz: int = 256, radius_ratio: float = 2.0,
                        Pr: float = 0.71, Ra: float = 1e5, seed: int = 1,
                        U: float = 0.05) -> dict:
