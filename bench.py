@@ -32,7 +32,7 @@ BYTES_PER_UPDATE = {"f32": 152, "f16": 76, "bf16": 76}
 
 
 STEP_SOURCES = ["paper_1806_10241_amd/csrc/axlb_node.h", "paper_1806_10241_amd/csrc/axlb_kernels.hip",
-                "paper_1806_10241_amd/csrc/axlb_device.h"]
+                "paper_1806_10241_amd/csrc/axlb_device.h", "paper_1806_10241_amd/csrc/axlb_twostep.hip"]
 
 
 def code_text(source: bytes) -> bytes:
@@ -55,12 +55,17 @@ def step_kernel_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(storage: str, Nr: int, Nz: int):
-    """HBM bytes per step-kernel launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size); None
-    unless that summary was taken on the current step-kernel sources and on
-    this workload."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_%dx%d_%s.md" % (Nr, Nz, storage))
+def profile_path(storage: str, Nr: int, Nz: int, layout: str) -> str:
+    suffix = "" if layout == "aa" else "_" + layout
+    return os.path.join(ROOT, "profiles", "step_kernel_%dx%d_%s%s.md" % (Nr, Nz, storage, suffix))
+
+
+def measured_traffic(storage: str, Nr: int, Nz: int, layout: str = "aa"):
+    """HBM bytes per launch of the dominant step kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of
+    known size); None unless that summary was taken on the current
+    step-kernel sources and on this workload."""
+    path = profile_path(storage, Nr, Nz, layout)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -299,6 +304,34 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, 
     return out
 
 
+def layout_trial(case, storage: str, steps: int = 60):
+    """ms per step of the single-buffer layout (256 x 1 tile) and of two steps
+    per launch on two buffers, on the workload, graph replays."""
+    import torch
+
+    from paper_1806_10241_amd import axlb
+    out = {}
+    for layout in ("aa", "ab2"):
+        stream = torch.cuda.Stream()
+        lat = axlb.Lattice(case, layout=layout, storage=storage, stream=stream)
+        if layout == "aa":
+            lat.set_tile(axlb_default_tile())
+        lat.step(20)
+        lat.prepare_steps(steps)
+        lat.sync()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        lat.step(steps)
+        b.record(stream)
+        b.synchronize()
+        out[layout] = a.elapsed_time(b) / steps
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    return out
+
+
 def headline(args, case, stream):
     """The timed run: warmup, then exactly args.steps steps replayed as
     graphs captured beforehand, bracketed by HIP events on the lattice's
@@ -319,6 +352,8 @@ def headline(args, case, stream):
         tune = {"%dx%d" % axlb.tile_shape(t): round(m * 1e3, 2) for t, m in enumerate(ms)}
         print("bench: autotune us/step per tile %s" % tune, file=sys.stderr, flush=True)
     _, tile_rz = lat.tile()
+    if args.single_launches:
+        lat.set_graphs(False)
     lat.step(args.warmup)
     if not args.single_launches:
         lat.prepare_steps(args.steps)
@@ -329,11 +364,7 @@ def headline(args, case, stream):
     end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     start.record(stream)
-    if args.single_launches:
-        for _ in range(args.steps):
-            lat.step(1)
-    else:
-        lat.step(args.steps)
+    lat.step(args.steps)
     end.record(stream)
     end.synchronize()
     torch.cuda.synchronize()
@@ -343,7 +374,8 @@ def headline(args, case, stream):
     lat.close()
     ms_per_step = ms / args.steps
     if args.single_launches:
-        launch = "one kernel launch per step"
+        launch = ("one two-step kernel launch per pair of steps" if args.layout == "ab2"
+                  else "one kernel launch per step")
     else:
         bundles, tail = divmod(args.steps, 100)
         parts = (["%d replays of a 100-step graph" % bundles] if bundles else []) + \
@@ -409,7 +441,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--layout", default="aa", choices=["aa", "ab", "ab2"])
+    ap.add_argument("--layout", default="auto", choices=["auto", "aa", "ab", "ab2"],
+                    help="streaming layout; auto: the faster of aa and ab2 on the workload")
     ap.add_argument("--deriv", default="lagged", choices=["lagged", "current"],
                     help="time level of the source-term derivatives (current needs --layout ab)")
     ap.add_argument("--Nr", type=int, default=1024)
@@ -477,6 +510,15 @@ def main():
     case = I.rotating_lid_cylinder(Nr=args.Nr, Nz=args.Nz, Re=1000.0, Ri=0.5,
                                    u_noise=args.u_noise)
     nodes = case["Nr"] * case["Nz"]
+    trials = None
+    if args.layout == "auto":
+        if args.deriv != "lagged":
+            args.layout = "ab"
+        else:
+            trials = layout_trial(case, args.storage)
+            args.layout = min(trials, key=trials.get)
+            print("bench: layout trials (ms/step) %s -> %s" % (trials, args.layout),
+                  file=sys.stderr, flush=True)
     h = headline(args, case, torch.cuda.Stream())
     ms_per_step = h["ms_per_step"]
     achieved = BYTES_PER_UPDATE[args.storage] * nodes / (ms_per_step / 1e3) / 1e9
@@ -499,6 +541,8 @@ def main():
                    "initial_noise": {"T": 1e-4, "u": args.u_noise},
                    "Nr": args.Nr, "Nz": args.Nz, "storage": args.storage,
                    "layout": args.layout, "derivatives": args.deriv,
+                   "layout_trials_ms_per_step": ({k: round(v, 5) for k, v in trials.items()}
+                                                 if trials else None),
                    "lag_storage": ("u_z, u_r, u_theta, T - T_ref as FP32: 16 B per node "
                                    "written and read per step" if args.storage == "f32" else
                                    "u_z, u_r, u_theta as binary16 (x 2^10), T - T_ref as FP32: "
@@ -507,8 +551,14 @@ def main():
                    "tile": h["tile"], "autotune_us_per_step": h["autotune_us_per_step"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": (measured_traffic(args.storage, args.Nr, args.Nz)
-                                 if args.layout == "aa" and args.deriv == "lagged" else None),
+                     "traffic": (measured_traffic(args.storage, args.Nr, args.Nz, args.layout)
+                                 if args.layout in ("aa", "ab2") and args.deriv == "lagged"
+                                 else None),
+                     "kernel": ("k_step_two (two steps per launch; achieved and traffic are per "
+                                "launch, algorithmic bytes 2 x %d B per node)"
+                                % BYTES_PER_UPDATE[args.storage] if args.layout == "ab2" else
+                                "k_step (one step per launch, %d B per node)"
+                                % BYTES_PER_UPDATE[args.storage]),
                      "working_set_bytes": working_set,
                      "cache_resident": working_set < 256e6,
                      "note": "algorithmic bytes (%d B per node update) over the measured step "

@@ -57,15 +57,16 @@ extern "C" {
 #define AXLB_LAYOUT_AB 1 /* two population buffers, pull streaming              */
 #define AXLB_LAYOUT_AB2 2 /* two buffers, two time steps per launch (below)     */
 /* AXLB_LAYOUT_AB2 holds the same two buffers as AB.  One launch advances two
- * time steps: a workgroup takes its tile and a one-node ring around it
- * through the first step, keeping the populations and lagged fields in
+ * time steps: a workgroup takes a 30 x 14 tile and the one-node ring around
+ * it through the first step, keeping the populations and lagged fields in
  * LDS, then takes its tile through the second step.  The results are
  * bit-identical to AB; each pair of steps reads and writes the state once.
- * An odd step count ends with one AB step.  Choosing a layout: while the
- * AA state (about 96 B per node in FP32) fits MI355X's 256 MB Infinity
- * Cache, AA is fastest; beyond it AB2 is, since HBM then carries every
- * byte and AB2 moves half as many per step (measured: 1024 x 2048 AA 37k
- * against AB2 35k MLUPS; 4096 x 4096 AA 27k against AB2 40k). */
+ * An odd step count ends with one AB step.  Choosing a layout: AB2 moves
+ * half the bytes per step and wins wherever the step is bound by memory
+ * (measured with FP32 storage: 1024 x 2048 AB2 38k against AA 35k MLUPS,
+ * 2048 x 4096 AB2 42k against AA 25k); with 16-bit storage, where the step
+ * is bound by latency and arithmetic, AA is faster at 1024 x 2048 (52k
+ * against 42k).  AA needs one population buffer instead of two. */
 
 /* ---- time level of the central differences in the geometric sources ----
  * (eq. 4b, 4c, 7, 9; Section 3.2 only says "central difference").
@@ -193,6 +194,10 @@ int axlb_set_fields(axlb_lattice *lat, const double *rho, const double *ur, cons
  * and is kept with the lattice (the 100-step bundles always, at most 8
  * other lengths).  Results are identical to one launch per step. */
 int axlb_step(axlb_lattice *lat, long n);
+/* Graph replay on (1, the default) or off (0): off, axlb_step makes one
+ * plain kernel launch per step (per pair of steps in AXLB_LAYOUT_AB2), for
+ * profilers that attribute counters to single dispatches.  Same results. */
+int axlb_set_graphs(axlb_lattice *lat, int enable);
 /* Captures, without running them, the graphs that axlb_step(lat, n) would
  * replay from the current state, so that a timed or latency-bound call
  * does not pay for the capture.  AXLB_ESTATE for a batch member. */
@@ -233,7 +238,7 @@ int axlb_load(axlb_lattice *lat, const void *host, size_t bytes);
  * it); axlb_autotune times every shape for steps_per_trial steps on the
  * lattice itself, restores the state it found, selects the fastest, and
  * returns the per-step times in ms_per_step[AXLB_NTILES] (may be NULL).
- * The two-step launches of AXLB_LAYOUT_AB2 use a fixed 32 x 8 tile; the
+ * The two-step launches of AXLB_LAYOUT_AB2 use a fixed 30 x 14 tile; the
  * selected shape applies to its single steps. */
 #define AXLB_NTILES 8
 int axlb_tile_shape(int tile, int *tile_r, int *tile_z);

@@ -42,7 +42,7 @@ EXPORTS = [
     "axlb_pool_create", "axlb_pool_set_policy", "axlb_pool_submit", "axlb_pool_tick",
     "axlb_pool_status",
     "axlb_pool_result", "axlb_pool_usage", "axlb_pool_destroy", "axlb_pool_last_error",
-    "axlb_nusselt_noalloc", "axlb_prepare_steps",
+    "axlb_nusselt_noalloc", "axlb_prepare_steps", "axlb_set_graphs",
 ]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 POOL_ORDER = {"fifo": 0, "smallest": 1}
@@ -108,6 +108,7 @@ def load():
         "axlb_set_fields": ([_vp] + [_dp] * 5, C.c_int),
         "axlb_step": ([_vp, C.c_long], C.c_int),
         "axlb_prepare_steps": ([_vp, C.c_long], C.c_int),
+        "axlb_set_graphs": ([_vp, C.c_int], C.c_int),
         "axlb_steps_done": ([_vp], C.c_long),
         "axlb_sync": ([_vp], C.c_int),
         "axlb_get_moments": ([_vp] + [_dp] * 5, C.c_int),
@@ -261,6 +262,10 @@ class Lattice:
 
     def step(self, n: int = 1):
         self._check(self._lib.axlb_step(self._h, int(n)))
+
+    def set_graphs(self, enable: bool):
+        """Graph replay on or off (off: one plain launch per step or pair)."""
+        self._check(self._lib.axlb_set_graphs(self._h, int(bool(enable))))
 
     def prepare_steps(self, n: int):
         """Captures the graphs that step(n) would replay from here."""

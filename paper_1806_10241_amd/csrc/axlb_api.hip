@@ -512,6 +512,12 @@ int axlb_step(axlb_lattice *L, long n) {
     return AXLB_OK;
 }
 
+int axlb_set_graphs(axlb_lattice *L, int enable) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    L->use_graphs = enable != 0;
+    return AXLB_OK;
+}
+
 int axlb_prepare_steps(axlb_lattice *L, long n) {
     if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
     if (n < 0) return fail(L, AXLB_EINVAL, "negative step count");

@@ -141,9 +141,11 @@ __device__ __forceinline__ float val_of(const KParams &P, int face) {
 // Storage conversions: FP32 arithmetic; FP32, binary16 or bfloat16 storage.
 // The 16-bit stores round stochastically, so that increments smaller than
 // half a 16-bit ulp survive in expectation instead of being rounded away
-// every step (see the 16-bit specialisations below).
+// every step (see the 16-bit specialisations below).  `rnd` is the store's
+// random word (slot_word for the stores of a node update, sr_single for a
+// lone value); FP32 ignores it.
 template <class S> struct Conv;
-// Conv<S>::bits(v, key, r) gives the bit pattern st stores for v; the
+// Conv<S>::bits(v, rnd, r) gives the bit pattern st stores for v; the
 // 16-bit conversions write it into the low half of the register r and leave
 // its high half as it was, so a sequence of stores can reuse one register
 // instead of clearing a fresh one for each.
@@ -157,14 +159,15 @@ template <> struct Conv<float> {
 // 16-bit stores round stochastically with the gfx950 conversions
 // v_cvt_sr_f16_f32 / v_cvt_sr_bf16_f32: the result rounds away from zero
 // with probability equal to the discarded fraction, the threshold coming
-// from the top bits of the random operand.  The operand is a multiplicative
-// hash of the value's bits and the slot key, whose top bits are the well
-// mixed ones: rounding is deterministic (a checkpoint replays bit for bit)
-// and fresh whenever the value changes.  NaN stays NaN; values beyond the
-// format's range become infinite.
+// from the top bits of the random operand.  The operand is derived from a
+// multiplicative hash of the stored values' bits and the node's position,
+// whose top bits are the well mixed ones: rounding is deterministic (a
+// checkpoint replays bit for bit) and fresh whenever a value changes.  NaN
+// stays NaN; values beyond the format's range become infinite.
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 typedef short short2_t __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ unsigned sr_bits(float x, unsigned key) {
+// Random word of a lone stored value with key `key`.
+__device__ __forceinline__ unsigned sr_single(float x, unsigned key) {
     return (__float_as_uint(x) ^ key) * 0x9E3779B1U;
 }
 
@@ -177,14 +180,13 @@ template <> struct Conv<__half> {
     __device__ static __forceinline__ float ld(const __half *p) {
         return f16_scaled(*p, 1.f / F16_SCALE);
     }
-    __device__ static __forceinline__ unsigned short bits(float v, unsigned key, Reg &r) {
-        const float x = v * F16_SCALE;
-        r = __builtin_amdgcn_cvt_sr_f16_f32(r, x, sr_bits(x, key), false);
+    __device__ static __forceinline__ unsigned short bits(float v, unsigned rnd, Reg &r) {
+        r = __builtin_amdgcn_cvt_sr_f16_f32(r, v * F16_SCALE, rnd, false);
         return __builtin_bit_cast(unsigned short, r[0]);
     }
-    __device__ static __forceinline__ void st(__half *p, float v, unsigned key) {
+    __device__ static __forceinline__ void st(__half *p, float v, unsigned rnd) {
         Reg r{0, 0};
-        *p = __builtin_bit_cast(__half, bits(v, key, r));
+        *p = __builtin_bit_cast(__half, bits(v, rnd, r));
     }
 };
 template <> struct Conv<__hip_bfloat16> {
@@ -192,13 +194,13 @@ template <> struct Conv<__hip_bfloat16> {
     __device__ static __forceinline__ float ld(const __hip_bfloat16 *p) {
         return __bfloat162float(*p);
     }
-    __device__ static __forceinline__ unsigned short bits(float v, unsigned key, Reg &r) {
-        r = __builtin_amdgcn_cvt_sr_bf16_f32(r, v, sr_bits(v, key), false);
+    __device__ static __forceinline__ unsigned short bits(float v, unsigned rnd, Reg &r) {
+        r = __builtin_amdgcn_cvt_sr_bf16_f32(r, v, rnd, false);
         return __builtin_bit_cast(unsigned short, r[0]);
     }
-    __device__ static __forceinline__ void st(__hip_bfloat16 *p, float v, unsigned key) {
+    __device__ static __forceinline__ void st(__hip_bfloat16 *p, float v, unsigned rnd) {
         Reg r{0, 0};
-        *p = __builtin_bit_cast(__hip_bfloat16, bits(v, key, r));
+        *p = __builtin_bit_cast(__hip_bfloat16, bits(v, rnd, r));
     }
 };
 

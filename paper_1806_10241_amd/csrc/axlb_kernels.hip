@@ -124,7 +124,8 @@ __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
         const double feq = rho * w1(ex, uz) * w1(ey, ur);
         const double w = w1(ex, 0.0) * w1(ey, 0.0);
         const int slot = AA ? Lat<FLOW>::opp(q) : q;
-        Conv<S>::st(A + slot * P.plane + n, (float)(feq - w), skey(i, j, q));
+        const float x = (float)(feq - w);
+        Conv<S>::st(A + slot * P.plane + n, x, sr_single(x, skey(i, j, q)));
     }
     const double psi = rho * uth;
     double ge[5], he[5];
@@ -142,9 +143,9 @@ __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
     for (int q = 0; q < 5; ++q) {
         const double w = q == 0 ? 1.0 / 3.0 : 1.0 / 6.0;
         const int slot = AA ? Lat<SWIRL>::opp(q) : q;
-        Conv<S>::st(A + (GOFF + slot) * P.plane + n, (float)ge[q], skey(i, j, GOFF + q));
-        Conv<S>::st(A + (HOFF + slot) * P.plane + n, (float)(he[q] - w * Tref),
-                    skey(i, j, HOFF + q));
+        const float xg = (float)ge[q], xh = (float)(he[q] - w * Tref);
+        Conv<S>::st(A + (GOFF + slot) * P.plane + n, xg, sr_single(xg, skey(i, j, GOFF + q)));
+        Conv<S>::st(A + (HOFF + slot) * P.plane + n, xh, sr_single(xh, skey(i, j, HOFF + q)));
     }
     lag_st<S>(M, 0, P.plane, n, (float)uz);
     lag_st<S>(M, 1, P.plane, n, (float)ur);

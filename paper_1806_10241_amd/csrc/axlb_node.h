@@ -43,10 +43,32 @@ static_assert(Lat<FLOW>::opp(1) == 3 && Lat<FLOW>::opp(2) == 4 && Lat<FLOW>::opp
               "D2Q9 opposite table");
 static_assert(Lat<SWIRL>::opp(1) == 3 && Lat<SWIRL>::opp(4) == 2, "D2Q5 opposite table");
 
-// Key of population plane q at node (i, j) for the stochastic rounding of
-// 16-bit stores (unused for FP32).
-__device__ __forceinline__ unsigned skey(int i, int j, int q) {
-    return ((unsigned)i * 0x9E3779B1U) ^ ((unsigned)j * 0x85EBCA77U) ^ ((unsigned)q * 0xC2B2AE3DU);
+// Random words of the stochastic rounding of 16-bit stores (ignored by FP32
+// storage).  A node update's 19 stores share one multiplicative hash of the
+// node's position and of the XOR of the bit patterns of the 19 FP32 values:
+// it changes whenever any value changes, and a change in a value's lowest
+// bits reaches the word's top bits, which set the threshold.  Store p (plane
+// 0..18) adds p + 1 steps of a Weyl sequence to it, so the slots of a node
+// draw different thresholds.  One quarter-rate 32-bit multiply per node;
+// the node key uses the full-rate 24-bit multiply.
+template <int N>
+__device__ __forceinline__ unsigned xor_bits(const float (&v)[N]) {
+    unsigned x = __float_as_uint(v[0]);
+#pragma unroll
+    for (int k = 1; k < N; ++k) x ^= __float_as_uint(v[k]);
+    return x;
+}
+__device__ __forceinline__ unsigned node_word(const float (&f)[9], const float (&g)[5],
+                                              const float (&h)[5], int i, int j) {
+    const unsigned key = __umul24((unsigned)i, 0x9E3779u) ^ __umul24((unsigned)j, 0x85EBCAu);
+    return (xor_bits(f) ^ xor_bits(g) ^ xor_bits(h) ^ key) * 0x9E3779B1U;
+}
+__device__ __forceinline__ unsigned slot_word(unsigned w, int p) {
+    return w + (unsigned)(p + 1) * 0x632BE5ABU;
+}
+// The key of a lone value at node (i, j), plane p (initial states).
+__device__ __forceinline__ unsigned skey(int i, int j, int p) {
+    return ((unsigned)i * 0x9E3779B1U) ^ ((unsigned)j * 0x85EBCA77U) ^ ((unsigned)p * 0xC2B2AE3DU);
 }
 
 __device__ __forceinline__ bool is_wall(int k) {
@@ -198,7 +220,8 @@ __device__ __forceinline__ void pull_all(const KParams &P, const Src &src, int i
 // Odd AA phase: post-collision f*_Q(i, j) = v goes to the slot from which
 // the next (even) phase reads it, by the same rules as pull_edge.
 template <class S, int FLD, int Q>
-__device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, float v) {
+__device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, float v,
+                                          unsigned w0) {
     using L = Lat<FLD>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
     int ti = i + ex;
@@ -223,32 +246,32 @@ __device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, 
             }
         }
         Conv<S>::st(A + (L::OFF + L::opp(Q)) * P.plane + (long long)i * P.pitch + j, w,
-                    skey(i, j, L::OFF + Q));
+                    slot_word(w0, L::OFF + Q));
         return;
     }
     if (fy >= 0) {  // axis: arrives at (i + e_x, j) with e_y reversed
         if (ti < 0) ti += P.Nz;
         else if (ti >= P.Nz) ti -= P.Nz;
         Conv<S>::st(A + (L::OFF + L::refl(Q)) * P.plane + (long long)ti * P.pitch + j,
-                    FLD == SWIRL ? -v : v, skey(i, j, L::OFF + Q));
+                    FLD == SWIRL ? -v : v, slot_word(w0, L::OFF + Q));
         return;
     }
     ti += ti < 0 ? P.Nz : -P.Nz;  // periodic
     Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, v,
-                skey(i, j, L::OFF + Q));
+                slot_word(w0, L::OFF + Q));
 }
 
 template <class S, int FLD, int Q>
-__device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float v) {
+__device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float v, unsigned w0) {
     using L = Lat<FLD>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
     const int ti = i + ex, tj = j + ey;
     if ((unsigned)ti < (unsigned)P.Nz && (unsigned)tj < (unsigned)P.Nr) {
         Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, v,
-                    skey(i, j, L::OFF + Q));
+                    slot_word(w0, L::OFF + Q));
         return;
     }
-    push_edge<S, FLD, Q>(P, A, i, j, v);
+    push_edge<S, FLD, Q>(P, A, i, j, v, w0);
 }
 
 // ----------------------------------------------------------------------------
@@ -529,10 +552,10 @@ __device__ __forceinline__ float pull_in(const KParams &P, const S *A, unsigned 
 }
 
 template <class S, int FLD, int Q>
-__device__ __forceinline__ void push_in(const KParams &P, S *A, unsigned n, int i, int j, float v) {
+__device__ __forceinline__ void push_in(const KParams &P, S *A, unsigned n, float v, unsigned w0) {
     using L = Lat<FLD>;
     const unsigned dn = (unsigned)(L::ex(Q) * P.pitch + L::ey(Q));
-    Conv<S>::st(A + (long long)(L::OFF + Q) * P.plane + (n + dn), v, skey(i, j, L::OFF + Q));
+    Conv<S>::st(A + (long long)(L::OFF + Q) * P.plane + (n + dn), v, slot_word(w0, L::OFF + Q));
 }
 
 template <class S, int MODE>
@@ -580,65 +603,67 @@ __device__ __forceinline__ void scatter(const KParams &P, S *A, int i, int j, bo
                                         const float (&f)[9], const float (&g)[5],
                                         const float (&h)[5]) {
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+    const unsigned w0 = node_word(f, g, h, i, j);
     if (MODE == MODE_AB) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Conv<S>::st(A + (long long)q * P.plane + n, f[q], skey(i, j, q));
+        for (int q = 0; q < 9; ++q)
+            Conv<S>::st(A + (long long)q * P.plane + n, f[q], slot_word(w0, q));
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            Conv<S>::st(A + (long long)(GOFF + q) * P.plane + n, g[q], skey(i, j, GOFF + q));
-            Conv<S>::st(A + (long long)(HOFF + q) * P.plane + n, h[q], skey(i, j, HOFF + q));
+            Conv<S>::st(A + (long long)(GOFF + q) * P.plane + n, g[q], slot_word(w0, GOFF + q));
+            Conv<S>::st(A + (long long)(HOFF + q) * P.plane + n, h[q], slot_word(w0, HOFF + q));
         }
     } else if (MODE == MODE_AA_EVEN) {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            Conv<S>::st(A + (long long)Lat<FLOW>::opp(q) * P.plane + n, f[q], skey(i, j, q));
+            Conv<S>::st(A + (long long)Lat<FLOW>::opp(q) * P.plane + n, f[q], slot_word(w0, q));
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             Conv<S>::st(A + (long long)(GOFF + Lat<SWIRL>::opp(q)) * P.plane + n, g[q],
-                        skey(i, j, GOFF + q));
+                        slot_word(w0, GOFF + q));
             Conv<S>::st(A + (long long)(HOFF + Lat<THERMAL>::opp(q)) * P.plane + n, h[q],
-                        skey(i, j, HOFF + q));
+                        slot_word(w0, HOFF + q));
         }
     } else if (interior) {
-        push_in<S, FLOW, 0>(P, A, n, i, j, f[0]);
-        push_in<S, FLOW, 1>(P, A, n, i, j, f[1]);
-        push_in<S, FLOW, 2>(P, A, n, i, j, f[2]);
-        push_in<S, FLOW, 3>(P, A, n, i, j, f[3]);
-        push_in<S, FLOW, 4>(P, A, n, i, j, f[4]);
-        push_in<S, FLOW, 5>(P, A, n, i, j, f[5]);
-        push_in<S, FLOW, 6>(P, A, n, i, j, f[6]);
-        push_in<S, FLOW, 7>(P, A, n, i, j, f[7]);
-        push_in<S, FLOW, 8>(P, A, n, i, j, f[8]);
-        push_in<S, SWIRL, 0>(P, A, n, i, j, g[0]);
-        push_in<S, SWIRL, 1>(P, A, n, i, j, g[1]);
-        push_in<S, SWIRL, 2>(P, A, n, i, j, g[2]);
-        push_in<S, SWIRL, 3>(P, A, n, i, j, g[3]);
-        push_in<S, SWIRL, 4>(P, A, n, i, j, g[4]);
-        push_in<S, THERMAL, 0>(P, A, n, i, j, h[0]);
-        push_in<S, THERMAL, 1>(P, A, n, i, j, h[1]);
-        push_in<S, THERMAL, 2>(P, A, n, i, j, h[2]);
-        push_in<S, THERMAL, 3>(P, A, n, i, j, h[3]);
-        push_in<S, THERMAL, 4>(P, A, n, i, j, h[4]);
+        push_in<S, FLOW, 0>(P, A, n, f[0], w0);
+        push_in<S, FLOW, 1>(P, A, n, f[1], w0);
+        push_in<S, FLOW, 2>(P, A, n, f[2], w0);
+        push_in<S, FLOW, 3>(P, A, n, f[3], w0);
+        push_in<S, FLOW, 4>(P, A, n, f[4], w0);
+        push_in<S, FLOW, 5>(P, A, n, f[5], w0);
+        push_in<S, FLOW, 6>(P, A, n, f[6], w0);
+        push_in<S, FLOW, 7>(P, A, n, f[7], w0);
+        push_in<S, FLOW, 8>(P, A, n, f[8], w0);
+        push_in<S, SWIRL, 0>(P, A, n, g[0], w0);
+        push_in<S, SWIRL, 1>(P, A, n, g[1], w0);
+        push_in<S, SWIRL, 2>(P, A, n, g[2], w0);
+        push_in<S, SWIRL, 3>(P, A, n, g[3], w0);
+        push_in<S, SWIRL, 4>(P, A, n, g[4], w0);
+        push_in<S, THERMAL, 0>(P, A, n, h[0], w0);
+        push_in<S, THERMAL, 1>(P, A, n, h[1], w0);
+        push_in<S, THERMAL, 2>(P, A, n, h[2], w0);
+        push_in<S, THERMAL, 3>(P, A, n, h[3], w0);
+        push_in<S, THERMAL, 4>(P, A, n, h[4], w0);
     } else {
-        push<S, FLOW, 0>(P, A, i, j, f[0]);
-        push<S, FLOW, 1>(P, A, i, j, f[1]);
-        push<S, FLOW, 2>(P, A, i, j, f[2]);
-        push<S, FLOW, 3>(P, A, i, j, f[3]);
-        push<S, FLOW, 4>(P, A, i, j, f[4]);
-        push<S, FLOW, 5>(P, A, i, j, f[5]);
-        push<S, FLOW, 6>(P, A, i, j, f[6]);
-        push<S, FLOW, 7>(P, A, i, j, f[7]);
-        push<S, FLOW, 8>(P, A, i, j, f[8]);
-        push<S, SWIRL, 0>(P, A, i, j, g[0]);
-        push<S, SWIRL, 1>(P, A, i, j, g[1]);
-        push<S, SWIRL, 2>(P, A, i, j, g[2]);
-        push<S, SWIRL, 3>(P, A, i, j, g[3]);
-        push<S, SWIRL, 4>(P, A, i, j, g[4]);
-        push<S, THERMAL, 0>(P, A, i, j, h[0]);
-        push<S, THERMAL, 1>(P, A, i, j, h[1]);
-        push<S, THERMAL, 2>(P, A, i, j, h[2]);
-        push<S, THERMAL, 3>(P, A, i, j, h[3]);
-        push<S, THERMAL, 4>(P, A, i, j, h[4]);
+        push<S, FLOW, 0>(P, A, i, j, f[0], w0);
+        push<S, FLOW, 1>(P, A, i, j, f[1], w0);
+        push<S, FLOW, 2>(P, A, i, j, f[2], w0);
+        push<S, FLOW, 3>(P, A, i, j, f[3], w0);
+        push<S, FLOW, 4>(P, A, i, j, f[4], w0);
+        push<S, FLOW, 5>(P, A, i, j, f[5], w0);
+        push<S, FLOW, 6>(P, A, i, j, f[6], w0);
+        push<S, FLOW, 7>(P, A, i, j, f[7], w0);
+        push<S, FLOW, 8>(P, A, i, j, f[8], w0);
+        push<S, SWIRL, 0>(P, A, i, j, g[0], w0);
+        push<S, SWIRL, 1>(P, A, i, j, g[1], w0);
+        push<S, SWIRL, 2>(P, A, i, j, g[2], w0);
+        push<S, SWIRL, 3>(P, A, i, j, g[3], w0);
+        push<S, SWIRL, 4>(P, A, i, j, g[4], w0);
+        push<S, THERMAL, 0>(P, A, i, j, h[0], w0);
+        push<S, THERMAL, 1>(P, A, i, j, h[1], w0);
+        push<S, THERMAL, 2>(P, A, i, j, h[2], w0);
+        push<S, THERMAL, 3>(P, A, i, j, h[3], w0);
+        push<S, THERMAL, 4>(P, A, i, j, h[4], w0);
     }
 }
 
@@ -735,9 +760,9 @@ __device__ __forceinline__ float ld_plane(const char *base, unsigned off) {
     return Conv<S>::ld(&v);
 }
 template <class S>
-__device__ __forceinline__ void st_plane(char *base, unsigned off, float x, unsigned key,
+__device__ __forceinline__ void st_plane(char *base, unsigned off, float x, unsigned rnd,
                                          typename Conv<S>::Reg &r) {
-    gstore(base, off, Conv<S>::bits(x, key, r));
+    gstore(base, off, Conv<S>::bits(x, rnd, r));
 }
 // A lagged velocity (format of population storage S) at byte offset off.
 template <class S>
@@ -765,12 +790,13 @@ __device__ __forceinline__ void scatter_planes(const Planes &A, unsigned o, int 
                                                const float (&f)[9], const float (&g)[5],
                                                const float (&h)[5]) {
     typename Conv<S>::Reg r{};
+    const unsigned w0 = node_word(f, g, h, i, j);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], o, f[q], skey(i, j, q), r);
+    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], o, f[q], slot_word(w0, q), r);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        st_plane<S>(A.wr[GOFF + q], o, g[q], skey(i, j, GOFF + q), r);
-        st_plane<S>(A.wr[HOFF + q], o, h[q], skey(i, j, HOFF + q), r);
+        st_plane<S>(A.wr[GOFF + q], o, g[q], slot_word(w0, GOFF + q), r);
+        st_plane<S>(A.wr[HOFF + q], o, h[q], slot_word(w0, HOFF + q), r);
     }
 }
 // A register copy of a byte offset that the compiler cannot trace back to

@@ -1,26 +1,32 @@
 // Two time steps per launch on two population buffers (gfx950), with the
-// lagged derivatives of the single-step kernels.  A workgroup owns a tile of
-// TWO_BX x TWO_BY nodes.  It first takes the tile and a one-node ring around
-// it through step t, reading the populations and lagged fields of the state
-// before t from device memory, and keeps the post-collision populations and
-// the half-step fields of every cell in LDS, rounded exactly as a store to
-// device memory would round them.  The ring cells are computed again by the
-// workgroups that own them (the price of the fusion); a cell beyond a
-// periodic z face holds the periodic image.  Then it takes its tile through
-// step t + 1 from LDS alone and writes the state after t + 1.  The per-node
-// arithmetic is the single-step kernels' (axlb_node.h), so the result equals
-// two single steps bit for bit, while the state crosses HBM once per pair.
-// Interior cells read, and the tile writes, through the plane addresses of
-// a two-buffer pull (Planes).
+// lagged derivatives of the single-step kernels.  A workgroup has one thread
+// per cell of a CW x CH block: a tile of (CW - 2) x (CH - 2) nodes and the
+// one-node ring around it.  Step t: every thread takes its cell from the
+// state before t (populations and lagged fields in device memory) and keeps
+// the post-collision populations and the half-step fields in LDS, rounded
+// exactly as a store to device memory would round them.  A ring cell is
+// computed again by the workgroup that owns it (the price of the fusion); a
+// cell beyond a periodic z face holds the periodic image.  Step t + 1: the
+// tile's threads take their nodes from LDS alone and write the state after
+// t + 1.  The per-node arithmetic is the single-step kernels' (axlb_node.h),
+// so the result equals two single steps bit for bit, while the state crosses
+// HBM once per pair.  Interior nodes (all eight neighbours fluid) read
+// device memory through the plane addresses of a two-buffer pull (Planes)
+// and LDS through fixed stencil offsets; only nodes on the lattice's edge
+// take the general boundary rules.
 #include "axlb_device.h"
 #include "axlb_launch.h"
 #include "axlb_node.h"
 
 namespace axlb {
 
-constexpr int TWO_BX = 32, TWO_BY = 8;
+// Cell block of a workgroup: one thread per cell; a wavefront holds two rows
+// of 32 cells.  Every thread computes one cell of step t; the 30 x 14 tile
+// of step t + 1 is 82% of them.
+constexpr int TWO_CW = 32, TWO_CH = 16;
+constexpr int TWO_TW = TWO_CW - 2, TWO_TH = TWO_CH - 2;
 
-// The LDS tile of post-collision populations as a population source for
+// The LDS block of post-collision populations as a population source for
 // pull_all: node (i, j) sits in cell (i - i0 + 1, j - j0 + 1).
 template <class S, int H, int W>
 struct TilePops {
@@ -31,79 +37,127 @@ struct TilePops {
     }
 };
 
-template <class S, int BX, int BY>
-__global__ void __launch_bounds__(BX * BY) k_step_two(const KParams P, const Planes A,
-                                                       const S *src, S *dst,
-                                                       const char *__restrict__ Mprev,
-                                                       char *__restrict__ Mnext) {
-    constexpr int W = BX + 2, H = BY + 2, NC = W * H;
+// Pull of population Q of distribution FLD from the LDS block for an
+// interior node in cell (a, b): the post-collision value of the neighbour
+// x - e_Q (two-buffer convention, plane Q).
+template <class S, int FLD, int Q, int H, int W>
+__device__ __forceinline__ float pull_lds(const S (&A)[NPOP][H][W], int a, int b) {
+    using L = Lat<FLD>;
+    return Conv<S>::ld(&A[L::OFF + Q][a - L::ex(Q)][b - L::ey(Q)]);
+}
+
+template <class S, int H, int W>
+__device__ __forceinline__ void pull_lds_all(const S (&A)[NPOP][H][W], int a, int b,
+                                             float (&f)[9], float (&g)[5], float (&h)[5]) {
+    f[0] = pull_lds<S, FLOW, 0>(A, a, b);
+    f[1] = pull_lds<S, FLOW, 1>(A, a, b);
+    f[2] = pull_lds<S, FLOW, 2>(A, a, b);
+    f[3] = pull_lds<S, FLOW, 3>(A, a, b);
+    f[4] = pull_lds<S, FLOW, 4>(A, a, b);
+    f[5] = pull_lds<S, FLOW, 5>(A, a, b);
+    f[6] = pull_lds<S, FLOW, 6>(A, a, b);
+    f[7] = pull_lds<S, FLOW, 7>(A, a, b);
+    f[8] = pull_lds<S, FLOW, 8>(A, a, b);
+    g[0] = pull_lds<S, SWIRL, 0>(A, a, b);
+    g[1] = pull_lds<S, SWIRL, 1>(A, a, b);
+    g[2] = pull_lds<S, SWIRL, 2>(A, a, b);
+    g[3] = pull_lds<S, SWIRL, 3>(A, a, b);
+    g[4] = pull_lds<S, SWIRL, 4>(A, a, b);
+    h[0] = pull_lds<S, THERMAL, 0>(A, a, b);
+    h[1] = pull_lds<S, THERMAL, 1>(A, a, b);
+    h[2] = pull_lds<S, THERMAL, 2>(A, a, b);
+    h[3] = pull_lds<S, THERMAL, 3>(A, a, b);
+    h[4] = pull_lds<S, THERMAL, 4>(A, a, b);
+}
+
+template <class S>
+__global__ void __launch_bounds__(TWO_CW *TWO_CH) k_step_two(const KParams P, const Planes A,
+                                                              const S *src, S *dst,
+                                                              const char *__restrict__ Mprev,
+                                                              char *__restrict__ Mnext) {
+    constexpr int W = TWO_CW, H = TWO_CH;
     __shared__ S pop[NPOP][H][W];
     __shared__ float lag[NLAG][H][W];
-    int i, j;
-    tile_of<BX, BY>(P, i, j);
-    const int tx = (int)threadIdx.x % BX, ty = (int)threadIdx.x / BX;
-    const int i0 = i - ty, j0 = j - tx;
+    // tile of this workgroup, XCD-banded as tile_of deals them
+    const int gx = (P.Nr + TWO_TW - 1) / TWO_TW;
+    const int nb = gx * ((P.Nz + TWO_TH - 1) / TWO_TH);
+    const int bid = (int)blockIdx.x, xcd = bid & 7, k = bid >> 3, q = nb >> 3, r = nb & 7;
+    const int t = xcd * q + (xcd < r ? xcd : r) + k;
+    const int i0 = (t / gx) * TWO_TH, j0 = (t % gx) * TWO_TW;
+    const int a = (int)threadIdx.x / W, b = (int)threadIdx.x % W;
 
-    // step t for every fluid cell of the tile and its ring: the interior
-    // nodes row by row (coalesced, pass 0), then the lattice's edge nodes
-    // column by column (pass 1), so that an edge column's cells share a few
-    // wavefronts and only those run the boundary code
-    for (int pass = 0; pass < 2; ++pass)
-    for (int c = (int)threadIdx.x; c < NC; c += BX * BY) {
-        const int a = pass == 0 ? c / W : c % H, b = pass == 0 ? c % W : c / H;
+    // step t for this thread's cell
+    {
         int ci = i0 - 1 + a;
         const int cj = j0 - 1 + b;
-        if ((unsigned)cj >= (unsigned)P.Nr) continue;
-        if ((unsigned)ci >= (unsigned)P.Nz) {
-            if (kind_of(P, ci < 0 ? Z_LO : Z_HI, FLOW) != PERIODIC) continue;
+        bool live = (unsigned)cj < (unsigned)P.Nr;
+        if (live && (unsigned)ci >= (unsigned)P.Nz) {
+            // beyond a z face: the periodic image, or nothing
+            live = kind_of(P, ci < 0 ? Z_LO : Z_HI, FLOW) == PERIODIC;
             ci += ci < 0 ? P.Nz : -P.Nz;
-            if ((unsigned)ci >= (unsigned)P.Nz) continue;
+            live = live && (unsigned)ci < (unsigned)P.Nz;
         }
-        const bool interior = interior_node(P, ci, cj);
-        if (interior != (pass == 0)) continue;
-        float f[9], g[5], h[5], d[5];
-        if (interior)
-            gather_planes<S>(A, ((unsigned)ci * (unsigned)P.pitch + (unsigned)cj) *
-                                    (unsigned)sizeof(S), f, g, h);
-        else
-            gather<S, MODE_AB>(P, src, ci, cj, false, f, g, h);
-        derivatives<S>(P, Mprev, ci, cj, interior, d);
-        const Half Hs = relax_node(P, cj, f, g, h, d);
+        if (live) {
+            const bool interior = interior_node(P, ci, cj);
+            float f[9], g[5], h[5], d[5];
+            if (interior)
+                gather_planes<S>(A, ((unsigned)ci * (unsigned)P.pitch + (unsigned)cj) *
+                                        (unsigned)sizeof(S), f, g, h);
+            else
+                gather<S, MODE_AB>(P, src, ci, cj, false, f, g, h);
+            derivatives<S>(P, Mprev, ci, cj, interior, d);
+            const Half Hs = relax_node(P, cj, f, g, h, d);
+            const unsigned w0 = node_word(f, g, h, ci, cj);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Conv<S>::st(&pop[q][a][b], f[q], skey(ci, cj, q));
+            for (int p = 0; p < 9; ++p) Conv<S>::st(&pop[p][a][b], f[p], slot_word(w0, p));
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            Conv<S>::st(&pop[GOFF + q][a][b], g[q], skey(ci, cj, GOFF + q));
-            Conv<S>::st(&pop[HOFF + q][a][b], h[q], skey(ci, cj, HOFF + q));
+            for (int p = 0; p < 5; ++p) {
+                Conv<S>::st(&pop[GOFF + p][a][b], g[p], slot_word(w0, GOFF + p));
+                Conv<S>::st(&pop[HOFF + p][a][b], h[p], slot_word(w0, HOFF + p));
+            }
+            lag[0][a][b] = lag_round<S>(0, Hs.ux);
+            lag[1][a][b] = lag_round<S>(1, Hs.uy);
+            lag[2][a][b] = lag_round<S>(2, Hs.psi * Hs.irho);
+            lag[3][a][b] = lag_round<S>(3, Hs.dphi);
         }
-        lag[0][a][b] = lag_round<S>(0, Hs.ux);
-        lag[1][a][b] = lag_round<S>(1, Hs.uy);
-        lag[2][a][b] = lag_round<S>(2, Hs.psi * Hs.irho);
-        lag[3][a][b] = lag_round<S>(3, Hs.dphi);
     }
     __syncthreads();
-    if (i >= P.Nz || j >= P.Nr) return;
 
-    // step t + 1 for the tile's own node, from LDS
+    // step t + 1 for the tile's own nodes, from LDS
+    if (a < 1 || a > TWO_TH || b < 1 || b > TWO_TW) return;
+    const int i = i0 - 1 + a, j = j0 - 1 + b;
+    if (i >= P.Nz || j >= P.Nr) return;
     float f[9], g[5], h[5], d[5];
-    pull_all<false>(P, TilePops<S, H, W>{pop, i0, j0}, i, j, f, g, h);
-    differences(P, TileSource<H, W>{lag, ty + 1, tx + 1}, i, j, d);
+    if (interior_node(P, i, j)) {
+        pull_lds_all<S>(pop, a, b, f, g, h);
+        d[0] = 0.5f * (lag[1][a + 1][b] - lag[1][a - 1][b]);
+        d[1] = 0.5f * (lag[0][a][b + 1] - lag[0][a][b - 1]);
+        d[2] = 0.5f * (lag[1][a][b + 1] - lag[1][a][b - 1]);
+        d[3] = 0.5f * (lag[2][a][b + 1] - lag[2][a][b - 1]);
+        d[4] = 0.5f * (lag[3][a][b + 1] - lag[3][a][b - 1]);
+    } else {
+        pull_all<false>(P, TilePops<S, H, W>{pop, i0, j0}, i, j, f, g, h);
+        differences(P, TileSource<H, W>{lag, a, b}, i, j, d);
+    }
     const Half Hs = relax_node(P, j, f, g, h, d);
+    using F = LagFmt<S>;
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
-    scatter_planes<S>(A, local_offset(n * (unsigned)sizeof(S)), i, j, f, g, h);
-    lag_st<S>(Mnext, 0, P.plane, n, Hs.ux);
-    lag_st<S>(Mnext, 1, P.plane, n, Hs.uy);
-    lag_st<S>(Mnext, 2, P.plane, n, Hs.psi * Hs.irho);
-    lag_st<S>(Mnext, 3, P.plane, n, Hs.dphi);
+    const unsigned so = local_offset(n * (unsigned)sizeof(S)), sov = local_offset(n * F::VB);
+    const unsigned so4 = local_offset(n * 4u);
+    scatter_planes<S>(A, so, i, j, f, g, h);
+    gstore(A.lwr[0], sov, F::enc(Hs.ux));
+    gstore(A.lwr[1], sov, F::enc(Hs.uy));
+    gstore(A.lwr[2], sov, F::enc(Hs.psi * Hs.irho));
+    gstore(A.lwr[3], so4, Hs.dphi);
 }
 
 template <class S>
 static hipError_t step_two_t(const KParams &P, const void *src, void *dst, const char *Mprev,
                              char *Mnext, hipStream_t st) {
-    const int gx = (P.Nr + TWO_BX - 1) / TWO_BX, gy = (P.Nz + TWO_BY - 1) / TWO_BY;
+    const int gx = (P.Nr + TWO_TW - 1) / TWO_TW, gy = (P.Nz + TWO_TH - 1) / TWO_TH;
     const Planes A = step_planes(P, store_of<S>(), MODE_AB, src, dst, Mprev, Mnext);
-    k_step_two<S, TWO_BX, TWO_BY><<<dim3(gx * gy), dim3(TWO_BX * TWO_BY), 0, st>>>(
-        P, A, (const S *)src, (S *)dst, Mprev, Mnext);
+    k_step_two<S><<<dim3(gx * gy), dim3(TWO_CW * TWO_CH), 0, st>>>(P, A, (const S *)src,
+                                                                   (S *)dst, Mprev, Mnext);
     return hipGetLastError();
 }
 

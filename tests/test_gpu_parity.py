@@ -484,3 +484,38 @@ def test_degenerate_cylinders_match_the_oracle(gpu, orc, shape):
         lat = axlb.Lattice(c, layout=layout)
         lat.step(300)
         assert_parity(lat.fields(), want, TOL["f32"], (shape, layout), TOL_DRHO["f32"])
+
+
+@pytest.fixture(scope="module")
+def steady_annulus(orc):
+    """A small annulus (32 x 32, Ra = 1e4, Nu about 3.07) run by the oracle
+    to a steady state (residual below 1e-10)."""
+    c = I.annulus_convection(Nr=32, Nz=32, Ra=1e4, seed=17)
+    L = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
+    prev, steps, r = L.fields(), 0, float("inf")
+    while steps < 200000 and r >= 1e-10:
+        L.step(2000)
+        steps += 2000
+        F = L.fields()
+        r = orc.residual(F, prev, 2000)
+        prev = F
+    assert r < 1e-10
+    return c, steps, L.nusselt()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16",
+                                     pytest.param("bf16", marks=BF16_XFAIL)])
+def test_steady_nusselt_matches_the_oracle(gpu, steady_annulus, storage):
+    """Steady wall Nusselt numbers with each storage against the oracle's:
+    16-bit rounding that correlated with the values would bias them here
+    (within 0.5%, FP32 within 1e-4)."""
+    c, steps, nu_ref = steady_annulus
+    say("steady Nusselt", storage, steps, "steps, oracle", nu_ref)
+    from paper_1806_10241_amd import axlb
+    lat = axlb.Lattice(c, storage=storage)
+    lat.step(steps)
+    nu = lat.nusselt()
+    err = [abs(x - y) / abs(y) for x, y in zip(nu, nu_ref)]
+    say("  Nu", nu, "rel errors", ["%.2e" % e for e in err])
+    bar = 1e-4 if storage == "f32" else NU_TOL
+    assert max(err) <= bar, (nu, nu_ref)
