@@ -221,13 +221,18 @@ def rotating_lid_cylinder(Nr: int = 1024, Nz: int = 2048, Re: float = 1000.0,
 
 
 def rayleigh_benard_cylinder(Nr: int = 100, Nz: int = 100, Pr: float = 0.7, Ra: float = 5e3,
-                             T_init: float = 0.0, seed: int = 6, U: float = 0.05) -> dict:
+                             T_init: float = 0.0, T0: float = 0.0, seed: int = 6,
+                             U: float = 0.05) -> dict:
     """Rayleigh-Benard convection in a closed vertical cylinder (Section 3.3):
     hot bottom lid T = 1, cold top lid T = 0, adiabatic no-slip side wall,
     axis by the mirror rule, gravity along -z.  R = Nr, H = Nz, Ra uses
     L = H and the free-fall velocity sqrt(g beta dT H) = U.  The fluid starts
     at rest at T_init (0: the cold start, 1: the hot start) plus seeded
-    noise of amplitude 1e-4."""
+    noise of amplitude 1e-4.  T0 is the reference temperature of the
+    Boussinesq force g beta (T - T0), which Section 3.3 leaves unstated:
+    T0 = T_L = 0 (the default) gives the cold start no initial buoyancy
+    force; T0 = 1/2, the mean temperature of Section 3.2, starts it under a
+    uniform downward force g beta dT / 2."""
     nu, alpha, Ra_eff = convection_velocity_scale_params(Nz, Pr, Ra, U)
     bc = {}
     _axis(bc)
@@ -239,7 +244,7 @@ def rayleigh_benard_cylinder(Nr: int = 100, Nz: int = 100, Pr: float = 0.7, Ra: 
     gbeta = U * U / Nz
     return dict(name="rayleigh_benard_cylinder", Nr=Nr, Nz=Nz, cylinder=1, r_inner=0.0,
                 nu=nu, alpha=alpha, Pr=nu / alpha, Ra=gbeta * Nr ** 3 / (nu * alpha),
-                Ra_H=Ra_eff, U_ff=U, g_axial=0.0, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5,
+                Ra_H=Ra_eff, U_ff=U, g_axial=0.0, T0=T0, omega3=1.0, bc=bc, T_ref=0.5,
                 seed=seed, fields=_perturbed_T(seed, Nz, Nr, base=T_init))
 
 

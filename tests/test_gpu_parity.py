@@ -112,11 +112,11 @@ def _developed(c, seed, T_init):
 
 def rb_cold_case():
     """Rayleigh-Benard convection in a cylinder (Section 3.3), cold fluid."""
-    return _developed(I.rayleigh_benard_cylinder(Nr=48, Nz=48, T_init=0.0, seed=21), 21, 0.0)
+    return _developed(I.rayleigh_benard_cylinder(Nr=48, Nz=48, T_init=0.0, T0=0.5, seed=21), 21, 0.0)
 
 
 def rb_hot_case():
-    return _developed(I.rayleigh_benard_cylinder(Nr=48, Nz=48, T_init=1.0, seed=22), 22, 1.0)
+    return _developed(I.rayleigh_benard_cylinder(Nr=48, Nz=48, T_init=1.0, T0=0.5, seed=22), 22, 1.0)
 
 
 def mixed_case():
