@@ -112,6 +112,12 @@ extern "C" {
                             (NOSLIP, DIRICHLET, OMEGA_R) and h must impose T (DIRICHLET);
                             their anti-bounce-back adds the advective part u_n^2 s_w.  No
                             case of the paper uses one                                  */
+#define AXLB_SLIP 8      /* f only, z faces: a flat free surface half-way between the last
+                            row and the next (Section 3.6, the melt surface beside the
+                            crystal): u_z = 0 and no shear stress, by specular reflection
+                            of the populations (the pull takes the post-collision
+                            population of the neighbour along r, with e_z reversed).  g and
+                            h on the face take wall rules (ADIABATIC for d u_theta/dz = 0) */
 
 typedef struct axlb_lattice axlb_lattice;
 
@@ -178,6 +184,26 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
  * z).  Only before the first step; AXLB_ESTATE afterwards. */
 int axlb_set_bc(axlb_lattice *lat, int face, int field, int kind, double value);
 
+/* Outer part of a z face (Section 3.6: the crystal covers the top for
+ * r < R_x, the free surface the rest).  From radial node `from` on
+ * (1 <= from < Nr, the same for all three fields), face AXLB_Z_LO or
+ * AXLB_Z_HI takes the rule (kind, value) for distribution `field` instead
+ * of the one axlb_set_bc gave it: f NOSLIP or SLIP; g NOSLIP, DIRICHLET,
+ * OMEGA_R or ADIABATIC; h DIRICHLET or ADIABATIC.  A DIRICHLET value may
+ * vary linearly with the radius, value + slope * r (r of the link's
+ * crossing, r0 + j + 1/2 along z); slope must be 0 for every other kind.
+ * A link crosses the face at radial position j - e_r/2 for a population
+ * that arrives at node column j with radial velocity e_r; it takes the
+ * outer rule when that position is >= from - 1/2, so that each link has
+ * one rule and mass is conserved where the parts meet.  Fields of the part
+ * not yet given are NOSLIP, NOSLIP, ADIABATIC.  Both parts of a split face
+ * must be walls or free surface (no PERIODIC, HALO or VELOCITY); a
+ * cylinder with a split lid has no Nusselt numbers (axlb_nusselt returns
+ * AXLB_ESTATE).  Only before the first step; AXLB_EINVAL for any other
+ * argument. */
+int axlb_set_bc_outer(axlb_lattice *lat, int face, int from, int field, int kind, double value,
+                      double slope);
+
 /* Axial body force per unit mass g_axial and Boussinesq reference T0
  * (eq. 5: F^b_x = g_axial + g beta (T - T0)).  Only before the first step. */
 int axlb_set_body_force(axlb_lattice *lat, double g_axial, double T0);
@@ -217,6 +243,18 @@ int axlb_get_moments(axlb_lattice *lat, double *rho, double *ur, double *uz, dou
  * Cylinder: a, b = bottom and top lid (both z walls must impose T).
  * mean = (a + b)/2.  Synchronous. */
 int axlb_nusselt(axlb_lattice *lat, double *nu_a, double *nu_b, double *mean);
+
+/* Stream function of the meridian flow (Section 3.6, Table 4): psi with
+ * d psi / d r = -r u_z (and d psi / d z = r u_r), 0 on the inner face (the
+ * axis, or R_i), integrated outward over the node cells by the midpoint
+ * rule on the fields of axlb_get_moments: psi[iz][ir] = -sum_{k <= ir}
+ * r_k u_z(iz, k), its value at r0 + ir + 1, the outer edge of the node's
+ * cell.  FP64 on the device, one thread per row.  psi (host, Nr * Nz
+ * doubles) receives the field, *psi_min and *psi_max its smallest and
+ * largest value (cells turning one way and the other); any pointer may be
+ * NULL.  The device buffer (Nr * Nz + 2 Nz doubles) is allocated on the
+ * first call and kept with the lattice.  Synchronous. */
+int axlb_stream_function(axlb_lattice *lat, double *psi, double *psi_min, double *psi_max);
 
 /* Convergence residual, FP64 on the device: the largest of
  * ||c_now - c_then||_2 / (K ||speed_now||_2) over the velocity components

@@ -22,7 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
-NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, VELOCITY = 0, 1, 2, 3, 4, 5, 7
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, VELOCITY, SLIP = 0, 1, 2, 3, 4, 5, 7, 8
 DERIV_CURRENT, DERIV_PREVIOUS = 1, 2
 
 
@@ -52,7 +52,7 @@ def build_native(path: str) -> str:
 
 
 class _BC(C.Structure):
-    _fields_ = [("kind", C.c_int), ("value", C.c_double)]
+    _fields_ = [("kind", C.c_int), ("value", C.c_double), ("slope", C.c_double)]
 
 
 class _Params(C.Structure):
@@ -62,7 +62,8 @@ class _Params(C.Structure):
                 ("omega8", C.c_double), ("omega_psi3", C.c_double),
                 ("omega_psi4", C.c_double), ("omega_phi3", C.c_double),
                 ("omega_phi4", C.c_double), ("g_axial", C.c_double), ("gbeta", C.c_double),
-                ("T0", C.c_double), ("deriv_mode", C.c_int), ("bc", (_BC * 3) * 4)]
+                ("T0", C.c_double), ("deriv_mode", C.c_int), ("bc", (_BC * 3) * 4),
+                ("split", C.c_int * 2), ("outer", (_BC * 3) * 2)]
 
 
 _lib = None
@@ -98,6 +99,7 @@ def _load(path: str | None = None):
         lib.orc_half_step.argtypes = [C.POINTER(_Params), C.c_double, _dp, _dp, _dp]
         lib.orc_residual.argtypes = [C.c_long] + [_dp] * 8 + [C.c_long]
         lib.orc_residual.restype = C.c_double
+        lib.orc_stream_function.argtypes = [C.c_void_p, _dp, _dp, _dp]
         lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_threads.restype = C.c_int
         if path is not None:
@@ -175,9 +177,18 @@ def params(case: dict, deriv_mode: int = DERIV_PREVIOUS) -> _Params:
     p.gbeta = float(case.get("Ra", 0.0)) * p.nu * p.alpha / float(p.Nr) ** 3
     p.T0 = float(case.get("T0", 0.0))
     p.deriv_mode = int(deriv_mode)
-    for (face, fld), (kind, value) in case["bc"].items():
-        p.bc[face][fld].kind = int(kind)
-        p.bc[face][fld].value = float(value)
+    def put(bc, rule):
+        bc.kind, bc.value = int(rule[0]), float(rule[1])
+        bc.slope = float(rule[2]) if len(rule) > 2 else 0.0
+
+    for (face, fld), rule in case["bc"].items():
+        put(p.bc[face][fld], rule)
+    # axial faces in two parts: case["split"][face] = first radial node of
+    # the outer part, case["outer"][(face, fld)] = its rule
+    for face, first in case.get("split", {}).items():
+        p.split[face - Z_LO] = int(first)
+    for (face, fld), rule in case.get("outer", {}).items():
+        put(p.outer[face - Z_LO][fld], rule)
     return p
 
 
@@ -246,6 +257,14 @@ class Lattice:
         a, b, m = C.c_double(), C.c_double(), C.c_double()
         self._lib.orc_nusselt(self._h, C.byref(a), C.byref(b), C.byref(m))
         return a.value, b.value, m.value
+
+    def stream_function(self):
+        """(psi [Nz, Nr] at the outer edge of each node's cell, min psi,
+        max psi)."""
+        psi = np.zeros(self.N)
+        lo, hi = C.c_double(), C.c_double()
+        self._lib.orc_stream_function(self._h, _ptr(psi), C.byref(lo), C.byref(hi))
+        return psi.reshape(self.Nz, self.Nr), lo.value, hi.value
 
     def all_finite(self) -> bool:
         return bool(self._lib.orc_all_finite(self._h))

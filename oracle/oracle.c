@@ -73,13 +73,33 @@ static int is_wall(int kind)
            kind == ORC_ADIABATIC || kind == ORC_VELOCITY;
 }
 
+/* Index of the direction that is q reflected across a line x = const. */
+static int reflect_x(const int *ex, const int *ey, int nq, int q)
+{
+    for (int b = 0; b < nq; ++b)
+        if (ex[b] == -ex[q] && ey[b] == ey[q]) return b;
+    return -1;
+}
+
+/* Rule of distribution fld on a face where a link crosses it at twice the
+ * radial column c2 (2j for a link along x into column j, 2j - e_y for a
+ * diagonal one): an axial face split at column s gives its outer rule to
+ * c2 >= 2s - 1. */
+static const orc_bc *rule(const orc_params *p, int face, int fld, int c2)
+{
+    if (face >= ORC_Z_LO) {
+        const int f = face - ORC_Z_LO;
+        if (p->split[f] > 0 && c2 >= 2 * p->split[f] - 1) return &p->outer[f][fld];
+    }
+    return &p->bc[face][fld];
+}
+
 /* Velocity normal to a face that imposes one (VELOCITY for f), as the
  * component along +y (radial faces) or +x (axial faces); 0 for walls at
- * rest. */
-static double normal_velocity(const orc_params *p, int face)
+ * rest and free surfaces.  bcf is the f rule where the link crosses. */
+static double normal_velocity(const orc_bc *bcf)
 {
-    const orc_bc *bc = &p->bc[face][ORC_FLOW];
-    return bc->kind == ORC_VELOCITY ? bc->value : 0.0;
+    return bcf->kind == ORC_VELOCITY ? bcf->value : 0.0;
 }
 
 /* Radial coordinate of node row j: nodes sit half a spacing off the wall
@@ -239,7 +259,7 @@ void orc_collide_adv(const double g[5], double s, double ux, double uy,
  * crosses the wall. */
 static double wall_scalar(const orc_bc *bc, double ym)
 {
-    if (bc->kind == ORC_DIRICHLET) return bc->value;
+    if (bc->kind == ORC_DIRICHLET) return bc->value + bc->slope * ym;
     if (bc->kind == ORC_OMEGA_R) return bc->value * ym;
     return 0.0; /* NOSLIP: a wall at rest */
 }
@@ -263,7 +283,12 @@ static double wall_scalar(const orc_bc *bc, double ym)
  *      population comes from the node shifted by e_x along the axis with
  *      its radial velocity reversed; g is odd there (u_theta = 0 on the
  *      axis) and takes a minus sign;
- *   3. periodic wrap along the axis. */
+ *   3. a free surface on an axial face (SLIP, Section 3.6: u_z = 0 and no
+ *      shear): specular reflection, from the node shifted by e_y along the
+ *      surface with the axial velocity reversed;
+ *   4. periodic wrap along the axis.
+ * On an axial face split into two parts, a link takes the rule of the part
+ * where it crosses the face. */
 static double pulled(const orc_state *s, int fld, int q, int i, int j)
 {
     const orc_params *p = &s->p;
@@ -277,13 +302,15 @@ static double pulled(const orc_state *s, int fld, int q, int i, int j)
     const int fy = sj < 0 ? ORC_R_IN : (sj >= p->Nr ? ORC_R_OUT : -1);
     const int fx = si < 0 ? ORC_Z_LO : (si >= p->Nz ? ORC_Z_HI : -1);
 
+    /* an axial face's rule is the one of the column where the link crosses */
+    const int c2 = 2 * j - ey[q];
     int wall = -1;
     if (fy >= 0 && is_wall(p->bc[fy][fld].kind)) wall = fy;
-    else if (fx >= 0 && is_wall(p->bc[fx][fld].kind)) wall = fx;
+    else if (fx >= 0 && is_wall(rule(p, fx, fld, c2)->kind)) wall = fx;
     if (wall >= 0) {
-        const orc_bc *bc = &p->bc[wall][fld];
+        const orc_bc *bc = rule(p, wall, fld, c2);
         const double own = post[node(s, i, j) * nq + opposite(ex, ey, nq, q)];
-        const double un = normal_velocity(p, wall);
+        const double un = normal_velocity(rule(p, wall, ORC_FLOW, c2));
         if (fld == ORC_FLOW) {
             const double w = phi1d(ex[q], 0.0) * phi1d(ey[q], 0.0); /* lattice weight */
             const double eu = wall <= ORC_R_OUT ? ey[q] * un : ex[q] * un;
@@ -298,6 +325,13 @@ static double pulled(const orc_state *s, int fld, int q, int i, int j)
         sj = j;
         if (fld == ORC_SWIRL) sign = -1.0;
     }
+    if (fx >= 0 && rule(p, fx, fld, c2)->kind == ORC_SLIP) {
+        /* free surface: specular reflection, the population comes from the
+         * node shifted by e_y along the surface with its axial velocity
+         * reversed (after the axis reflection, if the link crosses both) */
+        qs = reflect_x(ex, ey, nq, qs);
+        si = i;
+    }
     if (fx >= 0) si = (si + p->Nz) % p->Nz; /* periodic (walls handled above) */
     return sign * post[node(s, si, sj) * nq + qs];
 }
@@ -310,7 +344,8 @@ static double pulled(const orc_state *s, int fld, int q, int i, int j)
  * meridian velocities at a no-slip wall, 2 q_w - q_1 for an imposed u_theta
  * or T, q_1 for zero flux, and 2 u_w - q_1 for the normal velocity at a wall
  * that imposes one; at the axis even variables (u_x, T) take q_1 and odd
- * ones (u_y, u_theta) take -q_1; a periodic face wraps. */
+ * ones (u_y, u_theta) take -q_1; at a free surface u_x takes -q_1 and u_y
+ * q_1; a periodic face wraps. */
 static double neighbour(const orc_state *s, const double *F, int v, int i, int j,
                         int di, int dj)
 {
@@ -325,13 +360,14 @@ static double neighbour(const orc_state *s, const double *F, int v, int i, int j
     if (face < 0) return F[node(s, ni, nj) * 4 + v];
 
     const int fld = (v == VX || v == VY) ? ORC_FLOW : (v == VT ? ORC_SWIRL : ORC_THERMAL);
-    const orc_bc *bc = &p->bc[face][fld];
+    const orc_bc *bc = rule(p, face, fld, 2 * j);
     if (bc->kind == ORC_PERIODIC) return F[node(s, (ni + p->Nz) % p->Nz, nj) * 4 + v];
     if (bc->kind == ORC_MIRROR) return (v == VX || v == VP) ? q1 : -q1;
     if (bc->kind == ORC_ADIABATIC) return q1;
+    if (bc->kind == ORC_SLIP) return v == VX ? -q1 : q1; /* u_x = 0, d_x u_y = 0 */
     if (v == VX || v == VY) {
         const int normal = face <= ORC_R_OUT ? VY : VX;
-        return v == normal ? 2.0 * normal_velocity(p, face) - q1 : -q1;
+        return v == normal ? 2.0 * normal_velocity(bc) - q1 : -q1;
     }
     const double yw = y_of(s, j) + 0.5 * dj; /* wall radius, or y_j on an axial face */
     return 2.0 * wall_scalar(bc, yw) - q1;
@@ -574,6 +610,10 @@ void orc_nusselt(const orc_state *s, double *nu_a, double *nu_b, double *mean)
         }
         a = -Ri / (Nz * dT) * sa;
         b = -Ro / (Nz * dT) * sb;
+    } else if (p->split[0] || p->split[1] || p->bc[ORC_Z_LO][ORC_THERMAL].slope != 0.0 ||
+               p->bc[ORC_Z_HI][ORC_THERMAL].slope != 0.0) {
+        /* lids of more than one temperature: no Nusselt number is defined */
+        a = b = NAN;
     } else {
         const double Ta = p->bc[ORC_Z_LO][ORC_THERMAL].value;
         const double Tb = p->bc[ORC_Z_HI][ORC_THERMAL].value;
@@ -595,7 +635,56 @@ void orc_nusselt(const orc_state *s, double *nu_a, double *nu_b, double *mean)
     if (mean) *mean = 0.5 * (a + b);
 }
 
+/* Stream function of the meridian flow (Section 3.6): d psi / d y = -y u_x,
+ * integrated outward from the inner face by the midpoint rule over the node
+ * cells. */
+void orc_stream_function(const orc_state *s, double *psi, double *lo, double *hi)
+{
+    const int Nr = s->p.Nr, Nz = s->p.Nz;
+    double *ux = malloc(sizeof(double) * Nr * Nz);
+    orc_fields(s, NULL, NULL, ux, NULL, NULL);
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < Nz; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < Nr; ++j) {
+            acc -= y_of(s, j) * ux[node(s, i, j)];
+            if (psi) psi[node(s, i, j)] = acc;
+            if (acc < a) a = acc;
+            if (acc > b) b = acc;
+        }
+    }
+    free(ux);
+    if (lo) *lo = a;
+    if (hi) *hi = b;
+}
+
 /* ------------------------------------------------------------------------ */
+/* A rule that the distribution may take on the face. */
+static int rule_ok(const orc_bc *bc, int face, int fld)
+{
+    const int k = bc->kind;
+    if (face >= ORC_Z_LO && k == ORC_MIRROR) return 0;
+    if (fld == ORC_FLOW && is_wall(k) && k != ORC_NOSLIP && k != ORC_VELOCITY) return 0;
+    if (fld != ORC_FLOW && (k == ORC_VELOCITY || k == ORC_SLIP)) return 0;
+    if (k == ORC_SLIP && face < ORC_Z_LO) return 0;
+    if (fld == ORC_THERMAL && (k == ORC_NOSLIP || k == ORC_OMEGA_R)) return 0;
+    if (k < 0 || k > ORC_SLIP || k == 6) return 0;
+    if (!isfinite(bc->slope)) return 0;
+    if (bc->slope != 0.0 && !(k == ORC_DIRICHLET && face >= ORC_Z_LO)) return 0;
+    return 1;
+}
+
+/* The three rules of one face (or face part) agree on what the face is. */
+static int face_ok(const orc_bc b[3])
+{
+    const int w = is_wall(b[0].kind) || b[0].kind == ORC_SLIP;
+    if (is_wall(b[1].kind) != w || is_wall(b[2].kind) != w) return 0;
+    if (b[0].kind == ORC_VELOCITY &&
+        (b[1].kind == ORC_ADIABATIC || b[2].kind != ORC_DIRICHLET || !isfinite(b[0].value)))
+        return 0;
+    return 1;
+}
+
 static int valid(const orc_params *p)
 {
     if (p->Nr < 2 || p->Nz < 1) return 0;
@@ -614,22 +703,28 @@ static int valid(const orc_params *p)
             p->bc[ORC_R_IN][fld].kind == ORC_PERIODIC)
             return 0;
         for (int face = 0; face < 4; ++face) {
-            const int k = p->bc[face][fld].kind;
-            if (face >= ORC_Z_LO && k == ORC_MIRROR) return 0;
-            if (fld == ORC_FLOW && is_wall(k) && k != ORC_NOSLIP && k != ORC_VELOCITY) return 0;
-            if (fld != ORC_FLOW && k == ORC_VELOCITY) return 0;
-            if (fld == ORC_THERMAL && (k == ORC_NOSLIP || k == ORC_OMEGA_R)) return 0;
+            if (!rule_ok(&p->bc[face][fld], face, fld)) return 0;
+            if (face >= ORC_Z_LO && p->split[face - ORC_Z_LO] != 0 &&
+                !rule_ok(&p->outer[face - ORC_Z_LO][fld], face, fld))
+                return 0;
         }
     }
-    /* a face is a wall for all three distributions or for none; where fluid
-     * crosses it (VELOCITY), g and h carry imposed values */
+    /* a face is a wall (or a free surface) for all three distributions or
+     * for none; where fluid crosses it (VELOCITY), g and h carry imposed
+     * values */
     for (int face = 0; face < 4; ++face) {
-        const int w = is_wall(p->bc[face][0].kind);
-        if (is_wall(p->bc[face][1].kind) != w || is_wall(p->bc[face][2].kind) != w) return 0;
-        if (p->bc[face][0].kind == ORC_VELOCITY &&
-            (p->bc[face][1].kind == ORC_ADIABATIC || p->bc[face][2].kind != ORC_DIRICHLET ||
-             !isfinite(p->bc[face][0].value)))
-            return 0;
+        if (!face_ok(p->bc[face])) return 0;
+        if (face < ORC_Z_LO) continue;
+        const int sp = p->split[face - ORC_Z_LO];
+        if (sp == 0) continue;
+        /* a split face is solid or free surface in both parts, with no
+         * fluid crossing it */
+        if (sp < 1 || sp > p->Nr - 1 || !face_ok(p->outer[face - ORC_Z_LO])) return 0;
+        for (int fld = 0; fld < 3; ++fld) {
+            const int a = p->bc[face][fld].kind, b = p->outer[face - ORC_Z_LO][fld].kind;
+            if (!(is_wall(a) || a == ORC_SLIP) || !(is_wall(b) || b == ORC_SLIP)) return 0;
+            if (a == ORC_VELOCITY || b == ORC_VELOCITY) return 0;
+        }
     }
     return 1;
 }

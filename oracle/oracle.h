@@ -30,19 +30,25 @@ enum { ORC_FLOW = 0, ORC_SWIRL = 1, ORC_THERMAL = 2 };
  * (half-way between the last fluid node and the first solid node); VELOCITY
  * (f only) is a wall of the same kind through which the fluid crosses with
  * the imposed normal velocity `value` (along +y on radial faces, +x on axial
- * faces: an inlet or outlet), with g and h imposed there; MIRROR is the
- * symmetry axis; PERIODIC wraps the axial direction.  (6 is left unused so
- * that the numbering matches the HIP library's.) */
+ * faces: an inlet or outlet), with g and h imposed there; SLIP (f only, on
+ * axial faces) is a flat free surface, half-way like a wall: no flow
+ * through it and no shear stress on it (the melt surface of Section 3.6),
+ * with g and h wall rules; MIRROR is the symmetry axis; PERIODIC wraps the
+ * axial direction.  (6 is left unused so that the numbering matches the HIP
+ * library's.) */
 enum {
     ORC_NOSLIP = 0, ORC_PERIODIC = 1, ORC_MIRROR = 2,
-    ORC_DIRICHLET = 3, ORC_OMEGA_R = 4, ORC_ADIABATIC = 5, ORC_VELOCITY = 7
+    ORC_DIRICHLET = 3, ORC_OMEGA_R = 4, ORC_ADIABATIC = 5, ORC_VELOCITY = 7,
+    ORC_SLIP = 8
 };
 /* Fields inside the central differences of the sources:
  * 1 = output fields of the current step (after streaming, eq. 18, 35, 47),
  * 2 = pre-collision fields of the previous step (after eq. 21, 38, 48). */
 enum { ORC_DERIV_CURRENT = 1, ORC_DERIV_PREVIOUS = 2 };
 
-typedef struct { int kind; double value; } orc_bc;
+/* A boundary rule.  DIRICHLET on an axial face imposes value + slope * y
+ * (y the radius where a link crosses the face); slope is 0 elsewhere. */
+typedef struct { int kind; double value; double slope; } orc_bc;
 
 typedef struct {
     int Nr, Nz;
@@ -57,6 +63,15 @@ typedef struct {
     double T0;         /* Boussinesq reference temperature                */
     int deriv_mode;    /* ORC_DERIV_CURRENT or ORC_DERIV_PREVIOUS         */
     orc_bc bc[4][3];   /* [face][field]                                   */
+    /* Axial faces in two parts (Section 3.6: crystal and free surface on
+     * the top).  split[f] (f = 0: z_lo, 1: z_hi) = s in 1..Nr-1: a link
+     * that crosses the face at radial column c >= s - 1/2 (c = j for a
+     * link along x into node column j, j - e_y/2 for a diagonal one, so
+     * each link has one rule) takes outer[f][field], the others
+     * bc[face][field]; 0 leaves the face whole.  The derivative ghost of
+     * node column j takes the rule of column j. */
+    int split[2];
+    orc_bc outer[2][3];
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -77,6 +92,13 @@ void orc_fields(const orc_state *s, double *rho, double *ur, double *uz,
 /* Wall heat-transfer numbers.  Annulus: inner and outer cylinder.
  * Cylinder: bottom (z_lo) and top (z_hi) lids.  mean = (a + b) / 2. */
 void orc_nusselt(const orc_state *s, double *nu_a, double *nu_b, double *mean);
+/* Stream function of the meridian flow (Section 3.6, Table 4), defined by
+ * d psi / d y = -y u_x (and d psi / d x = y u_y) with psi = 0 on the inner
+ * face: psi[i][j] is its value at radius y_j + 1/2, the outer edge of node
+ * j's cell, -sum_{k <= j} y_k u_x(i, k) (midpoint rule over the cells, on
+ * the fields of orc_fields).  *lo, *hi = its smallest and largest value.
+ * Any pointer may be NULL. */
+void orc_stream_function(const orc_state *s, double *psi, double *lo, double *hi);
 /* 1 when every stored population is finite. */
 int orc_all_finite(const orc_state *s);
 

@@ -23,7 +23,7 @@ LAYOUT_AA, LAYOUT_AB, LAYOUT_AB2 = 0, 1, 2
 ANNULUS, CYLINDER = 0, 1
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
-NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, HALO, VELOCITY = 0, 1, 2, 3, 4, 5, 6, 7
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, HALO, VELOCITY, SLIP = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
 STORAGE = {"f32": F32, "f16": F16, "bf16": BF16}
 LAYOUT = {"aa": LAYOUT_AA, "ab": LAYOUT_AB, "ab2": LAYOUT_AB2}
@@ -42,7 +42,8 @@ EXPORTS = [
     "axlb_pool_create", "axlb_pool_set_policy", "axlb_pool_submit", "axlb_pool_tick",
     "axlb_pool_status",
     "axlb_pool_result", "axlb_pool_usage", "axlb_pool_destroy", "axlb_pool_last_error",
-    "axlb_nusselt_noalloc", "axlb_prepare_steps", "axlb_set_graphs",
+    "axlb_nusselt_noalloc", "axlb_prepare_steps", "axlb_set_graphs", "axlb_set_bc_outer",
+    "axlb_stream_function",
 ]
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 POOL_ORDER = {"fifo": 0, "smallest": 1}
@@ -104,6 +105,9 @@ def load():
                                  C.c_double, C.c_double, C.c_double, C.POINTER(Relax),
                                  C.POINTER(Options), C.POINTER(_vp)], C.c_int),
         "axlb_set_bc": ([_vp, C.c_int, C.c_int, C.c_int, C.c_double], C.c_int),
+        "axlb_set_bc_outer": ([_vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double],
+                              C.c_int),
+        "axlb_stream_function": ([_vp, _dp, _dp, _dp], C.c_int),
         "axlb_set_body_force": ([_vp, C.c_double, C.c_double], C.c_int),
         "axlb_set_fields": ([_vp] + [_dp] * 5, C.c_int),
         "axlb_step": ([_vp, C.c_long], C.c_int),
@@ -224,10 +228,19 @@ class Lattice:
                                      C.byref(opt), C.byref(self._h))
         if rc:
             raise AxlbError(rc, lib.axlb_last_error(None).decode())
-        for (face, fld), (kind, value) in sorted(case["bc"].items()):
+        for (face, fld), rule in sorted(case["bc"].items()):
+            kind, value = rule[0], rule[1]
+            if len(rule) > 2 and rule[2] != 0.0:
+                raise ValueError("a sloped value is only for the outer part of a z face")
             if kind == MIRROR:
                 continue  # the axis of a cylinder is set by the library
             self._check(lib.axlb_set_bc(self._h, face, fld, kind, float(value)))
+        # z faces in two parts: case["split"][face] = first radial node of the
+        # outer part, case["outer"][(face, fld)] = (kind, value[, slope])
+        for (face, fld), rule in sorted(case.get("outer", {}).items()):
+            slope = float(rule[2]) if len(rule) > 2 else 0.0
+            self._check(lib.axlb_set_bc_outer(self._h, face, int(case["split"][face]), fld,
+                                              rule[0], float(rule[1]), slope))
         self._check(lib.axlb_set_body_force(self._h, float(case.get("g_axial", 0.0)),
                                             float(case.get("T0", 0.5))))
         if init_fields and case.get("fields") is not None:
@@ -288,6 +301,15 @@ class Lattice:
         a, b, m = C.c_double(), C.c_double(), C.c_double()
         self._check(self._lib.axlb_nusselt(self._h, C.byref(a), C.byref(b), C.byref(m)))
         return a.value, b.value, m.value
+
+    def stream_function(self):
+        """(psi [Nz, Nr] at the outer edge of each node's cell, min psi,
+        max psi) of the meridian flow (axlb_stream_function)."""
+        psi = np.empty(self.N)
+        lo, hi = C.c_double(), C.c_double()
+        self._check(self._lib.axlb_stream_function(self._h, _ptr(psi), C.byref(lo),
+                                                   C.byref(hi)))
+        return psi.reshape(self.Nz, self.Nr), lo.value, hi.value
 
     def nusselt_noalloc(self):
         """The wall Nusselt numbers through the entry point that allocates

@@ -103,6 +103,15 @@ KParams axlb::make_params(const axlb_lattice *L) {
         P.halo_pop[f] = L->halo[f];
         P.halo_lag[f] = L->halo[f] + L->lay.halo_pop_bytes;
     }
+    P.okinds = 0;
+    for (int f = 0; f < 2; ++f) {
+        P.split[f] = L->split[f];
+        for (int d = 0; d < 3; ++d) {
+            P.okinds |= (unsigned)(L->okind[f][d] & 15) << (4 * (3 * f + d));
+            P.oval[f][d] = (float)L->oval[f][d];
+            P.oslope[f][d] = (float)L->oslope[f][d];
+        }
+    }
     return P;
 }
 
@@ -117,7 +126,7 @@ static int check_bcs(axlb_lattice *L) {
     }
     bool halo = false;
     for (int f = 0; f < 4; ++f) {
-        const bool w = is_wall(L->kind[f][0]);
+        const bool w = is_wall(L->kind[f][0]) || L->kind[f][0] == AXLB_SLIP;
         const bool p = L->kind[f][0] == AXLB_PERIODIC;
         const bool h = L->kind[f][0] == AXLB_HALO;
         halo = halo || h;
@@ -133,6 +142,26 @@ static int check_bcs(axlb_lattice *L) {
             (L->kind[f][1] == AXLB_ADIABATIC || L->kind[f][2] != AXLB_DIRICHLET))
             return fail(L, AXLB_EINVAL,
                         "a VELOCITY face needs imposed u_theta (g) and imposed T (h)");
+    // a free surface carries wall rules for g and h
+    for (int f = AXLB_Z_LO; f <= AXLB_Z_HI; ++f)
+        if (L->kind[f][0] == AXLB_SLIP && (!is_wall(L->kind[f][1]) || !is_wall(L->kind[f][2])))
+            return fail(L, AXLB_EINVAL, "a SLIP face needs wall rules for g and h");
+    // split axial faces: both parts solid or free surface, no fluid crossing
+    for (int f = 0; f < 2; ++f) {
+        if (L->split[f] == 0) continue;
+        if (L->split[f] >= L->Nr)
+            return fail(L, AXLB_EINVAL, "the outer part of an axial face starts beyond the lattice");
+        const int face = AXLB_Z_LO + f;
+        for (int d = 0; d < 3; ++d) {
+            const int a = L->kind[face][d], b = L->okind[f][d];
+            const bool fa = d == 0 ? (a == AXLB_NOSLIP || a == AXLB_SLIP) : is_wall(a);
+            const bool fb = d == 0 ? (b == AXLB_NOSLIP || b == AXLB_SLIP) : is_wall(b);
+            if (!fa || !fb)
+                return fail(L, AXLB_EINVAL,
+                            "a split axial face is NOSLIP or SLIP for f and a wall for g and h "
+                            "in both parts");
+        }
+    }
     if (halo && (L->layout != AXLB_LAYOUT_AB || L->deriv != AXLB_DERIV_LAGGED))
         return fail(L, AXLB_EINVAL, "HALO faces need the two-buffer, one-step layout");
     return AXLB_OK;
@@ -409,8 +438,10 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
 int axlb_set_bc(axlb_lattice *L, int face, int field, int kind, double value) {
     if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
     if (L->started) return fail(L, AXLB_ESTATE, "boundary rules are fixed once stepping started");
-    if (face < 0 || face > 3 || field < 0 || field > 2 || kind < 0 || kind > 7)
+    if (face < 0 || face > 3 || field < 0 || field > 2 || kind < 0 || kind > 8)
         return fail(L, AXLB_EINVAL, "face, field or kind out of range");
+    if (kind == AXLB_SLIP && (field != AXLB_FLOW || face < AXLB_Z_LO))
+        return fail(L, AXLB_EINVAL, "SLIP is a rule for f (FLOW) on z faces");
     if (L->cylinder && face == AXLB_R_IN && kind != AXLB_MIRROR)
         return fail(L, AXLB_EINVAL, "the inner face of a cylinder is the axis");
     if (kind == AXLB_MIRROR && !(L->cylinder && face == AXLB_R_IN))
@@ -431,6 +462,44 @@ int axlb_set_bc(axlb_lattice *L, int face, int field, int kind, double value) {
         return fail(L, AXLB_EINVAL, "OMEGA_R value must be finite or NaN");
     L->kind[face][field] = kind;
     L->val[face][field] = value;
+    L->P = make_params(L);
+    return AXLB_OK;
+}
+
+int axlb_set_bc_outer(axlb_lattice *L, int face, int from, int field, int kind, double value,
+                      double slope) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    if (L->started) return fail(L, AXLB_ESTATE, "boundary rules are fixed once stepping started");
+    if (face != AXLB_Z_LO && face != AXLB_Z_HI)
+        return fail(L, AXLB_EINVAL, "only z faces have an outer part");
+    if (field < 0 || field > 2) return fail(L, AXLB_EINVAL, "field out of range");
+    const int f = face - AXLB_Z_LO;
+    if (from < 1 || from >= L->Nr)
+        return fail(L, AXLB_EINVAL, "the outer part must start at radial node 1 .. Nr - 1");
+    if (L->split[f] != 0 && L->split[f] != from)
+        return fail(L, AXLB_EINVAL, "an axial face splits at one radial node for all fields");
+    const bool ok = field == AXLB_FLOW ? (kind == AXLB_NOSLIP || kind == AXLB_SLIP)
+                  : field == AXLB_SWIRL
+                        ? (kind == AXLB_NOSLIP || kind == AXLB_DIRICHLET || kind == AXLB_OMEGA_R ||
+                           kind == AXLB_ADIABATIC)
+                        : (kind == AXLB_DIRICHLET || kind == AXLB_ADIABATIC);
+    if (!ok) return fail(L, AXLB_EINVAL, "kind not allowed on the outer part for this field");
+    if (!std::isfinite(value) || !std::isfinite(slope))
+        return fail(L, AXLB_EINVAL, "value and slope must be finite");
+    if (slope != 0.0 && kind != AXLB_DIRICHLET)
+        return fail(L, AXLB_EINVAL, "a slope is only for DIRICHLET");
+    // parts of a split face not yet given a rule are NOSLIP / NOSLIP /
+    // ADIABATIC, as a wall is by default
+    if (L->split[f] == 0) {
+        L->okind[f][0] = AXLB_NOSLIP;
+        L->okind[f][1] = AXLB_NOSLIP;
+        L->okind[f][2] = AXLB_ADIABATIC;
+        for (int d = 0; d < 3; ++d) L->oval[f][d] = L->oslope[f][d] = 0.0;
+    }
+    L->split[f] = from;
+    L->okind[f][field] = kind;
+    L->oval[f][field] = value;
+    L->oslope[f][field] = slope;
     L->P = make_params(L);
     return AXLB_OK;
 }
@@ -564,6 +633,8 @@ int axlb_nusselt(axlb_lattice *L, double *nu_a, double *nu_b, double *mean) {
     const int fa = L->cylinder ? AXLB_Z_LO : AXLB_R_IN, fb = L->cylinder ? AXLB_Z_HI : AXLB_R_OUT;
     if (L->kind[fa][2] != AXLB_DIRICHLET || L->kind[fb][2] != AXLB_DIRICHLET)
         return fail(L, AXLB_ESTATE, "Nusselt numbers need imposed T on both heat-transfer walls");
+    if (L->cylinder && (L->split[0] || L->split[1]))
+        return fail(L, AXLB_ESTATE, "Nusselt numbers need lids of one temperature each");
     const double Ta = L->val[fa][2], Tb = L->val[fb][2];
     const double dT = L->cylinder ? Tb - Ta : Ta - Tb;
     if (dT == 0.0) return fail(L, AXLB_ESTATE, "the two wall temperatures are equal");
@@ -595,6 +666,33 @@ int axlb_nusselt(axlb_lattice *L, double *nu_a, double *nu_b, double *mean) {
     if (nu_a) *nu_a = a;
     if (nu_b) *nu_b = b;
     if (mean) *mean = 0.5 * (a + b);
+    return AXLB_OK;
+}
+
+int axlb_stream_function(axlb_lattice *L, double *psi, double *psi_min, double *psi_max) {
+    if (!L) return fail(nullptr, AXLB_EINVAL, "lattice is NULL");
+    int rc = set_device(L);
+    if (rc) return rc;
+    const size_t N = (size_t)L->Nr * L->Nz;
+    if (!L->psi) HIP_TRY(L, hipMalloc((void **)&L->psi, (N + 2 * (size_t)L->Nz) * sizeof(double)));
+    rc = compute_fields(L);
+    if (rc) return rc;
+    const double r0 = L->cylinder ? 0.0 : L->r_inner;
+    hipError_t e = launch_stream(L->fld + 2 * N, L->Nr, L->Nz, r0, L->psi, L->psi + N, L->stream);
+    if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("stream function launch: ") + hipGetErrorString(e));
+    std::vector<double> rows(2 * (size_t)L->Nz);
+    HIP_TRY(L, hipMemcpyAsync(rows.data(), L->psi + N, rows.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, L->stream));
+    if (psi)
+        HIP_TRY(L, hipMemcpyAsync(psi, L->psi, N * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    HIP_TRY(L, hipStreamSynchronize(L->stream));
+    double lo = 0.0, hi = 0.0;
+    for (int i = 0; i < L->Nz; ++i) {
+        lo = std::fmin(lo, rows[2 * (size_t)i]);
+        hi = std::fmax(hi, rows[2 * (size_t)i + 1]);
+    }
+    if (psi_min) *psi_min = lo;
+    if (psi_max) *psi_max = hi;
     return AXLB_OK;
 }
 
@@ -708,6 +806,7 @@ int axlb_destroy(axlb_lattice *L) {
     (void)hipSetDevice(L->device);
     if (L->stream) (void)hipStreamSynchronize(L->stream);
     drop_graphs(L);
+    if (L->psi) (void)hipFree(L->psi);
     if (L->own_mem && L->base) (void)hipFree(L->base);
     if (L->own_stream && L->stream) (void)hipStreamDestroy(L->stream);
     delete L;

@@ -13,7 +13,7 @@ enum { R_IN = 0, R_OUT = 1, Z_LO = 2, Z_HI = 3 };
 enum { FLOW = 0, SWIRL = 1, THERMAL = 2 };
 enum {
     NOSLIP = 0, PERIODIC = 1, MIRROR = 2, DIRICHLET = 3, OMEGA_R = 4, ADIABATIC = 5, HALO = 6,
-    VELOCITY = 7
+    VELOCITY = 7, SLIP = 8
 };
 
 // Plane numbering of the population buffer: f_0..f_8, g_0..g_4, h_0..h_4.
@@ -100,6 +100,13 @@ struct KParams {
     unsigned long long kinds;         // boundary kind of (face, field) in bits
                                       // 4 (3 face + field) .. +3
     float val[4][3];                  // imposed u_theta / T, or Omega
+    // Axial faces in two parts: links that cross face Z_LO + f at twice
+    // the radial column c2 >= 2 split[f] - 1 take the outer rule (kinds in
+    // okinds, bits 4 (3 f + field) .. +3; value oval + oslope * r); split 0
+    // leaves the face whole.
+    int split[2];
+    unsigned okinds;
+    float oval[2][3], oslope[2][3];
     // HALO z faces (index 0: Z_LO, 1: Z_HI): the neighbouring row of the
     // adjacent slab, populations as 19 planes of `pitch` elements of the
     // storage type, then its lagged fields as a block of `pitch`-element
@@ -136,6 +143,30 @@ template <int FLD>
 __device__ __forceinline__ float val_of(const KParams &P, int face) {
     return face == 0 ? P.val[0][FLD] : face == 1 ? P.val[1][FLD] : face == 2 ? P.val[2][FLD]
                                                                              : P.val[3][FLD];
+}
+
+// Whether a link that crosses `face` at twice the radial column c2 (2 j for
+// a link along x into column j, 2 j - e_y for a diagonal one) meets the
+// outer part of a split axial face.
+__device__ __forceinline__ bool outer_part(const KParams &P, int face, int c2) {
+    if (face < Z_LO) return false;
+    const int s = face == Z_LO ? P.split[0] : P.split[1];
+    return s > 0 && c2 >= 2 * s - 1;
+}
+
+// Kind of the rule of distribution fld where a link crosses `face` at c2.
+__device__ __forceinline__ int kind_at(const KParams &P, int face, int fld, int c2) {
+    return outer_part(P, face, c2) ? (int)((P.okinds >> (4 * (3 * (face - Z_LO) + fld))) & 15u)
+                                   : kind_of(P, face, fld);
+}
+
+// Value of the rule of distribution FLD where a link crosses `face` at c2,
+// at radius ym (a sloped value on an outer part).
+template <int FLD>
+__device__ __forceinline__ float val_at(const KParams &P, int face, int c2, float ym) {
+    if (!outer_part(P, face, c2)) return val_of<FLD>(P, face);
+    return face == Z_LO ? P.oval[0][FLD] + P.oslope[0][FLD] * ym
+                        : P.oval[1][FLD] + P.oslope[1][FLD] * ym;
 }
 
 // Storage conversions: FP32 arithmetic; FP32, binary16 or bfloat16 storage.

@@ -37,6 +37,12 @@ struct axlb_lattice {
     int cur = 0;  // two-buffer layouts: the population and lagged-field pair the next step reads
     int kind[4][3]{};
     double val[4][3]{};
+    // outer parts of split axial faces (index 0: Z_LO, 1: Z_HI): from radial
+    // node split[f] on (0: the face is whole), rule okind / oval + oslope r
+    int split[2]{};
+    int okind[2][3]{};
+    double oval[2][3]{}, oslope[2][3]{};
+    double *psi = nullptr;  // stream function and row maxima (device, on demand)
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false, own_mem = false;

@@ -229,6 +229,28 @@ __global__ void __launch_bounds__(RED_THREADS) k_nusselt(const double *__restric
     }
 }
 
+// Stream function of the meridian flow, one thread per row i: psi(i, j) =
+// -sum_{k <= j} y_k u_z(i, k) (d psi / d y = -y u_x by the midpoint rule
+// over the node cells, 0 on the inner face), and the row's smallest and
+// largest value (row_range[2 i], row_range[2 i + 1]).
+__global__ void __launch_bounds__(RED_THREADS) k_stream(const double *__restrict__ uz, int Nr,
+                                                        int Nz, double r0, double *psi,
+                                                        double *row_range) {
+    const int i = (int)blockIdx.x * RED_THREADS + (int)threadIdx.x;
+    if (i >= Nz) return;
+    const double *u = uz + (long long)i * Nr;
+    double *out = psi + (long long)i * Nr;
+    double acc = 0.0, lo = 0.0, hi = 0.0;
+    for (int j = 0; j < Nr; ++j) {
+        acc -= (r0 + j + 0.5) * u[j];
+        out[j] = acc;
+        lo = fmin(lo, acc);
+        hi = fmax(hi, acc);
+    }
+    row_range[2 * i] = lo;
+    row_range[2 * i + 1] = hi;
+}
+
 // ----------------------------------------------------------------------------
 // Host-side launchers.
 static dim3 grid_for(const KParams &P, int bx, int by) {
@@ -387,6 +409,13 @@ hipError_t launch_residual(const double *fld, const double *snap, long long N, d
 hipError_t launch_nusselt(const double *T, int Nr, int Nz, int cylinder, double r0, double Ta,
                           double Tb, double *out2, hipStream_t st) {
     k_nusselt<<<1, RED_THREADS, 0, st>>>(T, Nr, Nz, cylinder, r0, Ta, Tb, out2);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream(const double *uz, int Nr, int Nz, double r0, double *psi,
+                         double *row_range, hipStream_t st) {
+    k_stream<<<(Nz + RED_THREADS - 1) / RED_THREADS, RED_THREADS, 0, st>>>(uz, Nr, Nz, r0, psi,
+                                                                          row_range);
     return hipGetLastError();
 }
 

@@ -51,5 +51,7 @@ hipError_t launch_residual(const double *fld, const double *snap, long long N, d
                            int nblocks, double *out9, hipStream_t st);
 hipError_t launch_nusselt(const double *T, int Nr, int Nz, int cylinder, double r0, double Ta,
                           double Tb, double *out2, hipStream_t st);
+hipError_t launch_stream(const double *uz, int Nr, int Nz, double r0, double *psi,
+                         double *row_range, hipStream_t st);
 
 }  // namespace axlb

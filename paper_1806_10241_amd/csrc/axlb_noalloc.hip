@@ -176,6 +176,8 @@ extern "C" int axlb_nusselt_noalloc(axlb_lattice *L, double *nu_a, double *nu_b,
     const int fa = L->cylinder ? AXLB_Z_LO : AXLB_R_IN, fb = L->cylinder ? AXLB_Z_HI : AXLB_R_OUT;
     if (L->kind[fa][2] != AXLB_DIRICHLET || L->kind[fb][2] != AXLB_DIRICHLET)
         return nu_fail(L, AXLB_ESTATE, "Nusselt numbers need imposed T on both heat-transfer walls");
+    if (L->cylinder && (L->split[0] || L->split[1]))
+        return nu_fail(L, AXLB_ESTATE, "Nusselt numbers need lids of one temperature each");
     const double Ta = L->val[fa][2], Tb = L->val[fb][2];
     const double dT = L->cylinder ? Tb - Ta : Ta - Tb;
     if (dT == 0.0) return nu_fail(L, AXLB_ESTATE, "the two wall temperatures are equal");

@@ -27,6 +27,9 @@ template <> struct Lat<FLOW> {
     __host__ __device__ static constexpr int refl(int q) {  // e_y -> -e_y
         return q == 2 ? 4 : q == 4 ? 2 : q == 5 ? 8 : q == 8 ? 5 : q == 6 ? 7 : q == 7 ? 6 : q;
     }
+    __host__ __device__ static constexpr int reflx(int q) {  // e_x -> -e_x
+        return q == 1 ? 3 : q == 3 ? 1 : q == 5 ? 6 : q == 6 ? 5 : q == 7 ? 8 : q == 8 ? 7 : q;
+    }
 };
 template <int OFFSET> struct Lat5 {
     static constexpr int NQ = 5, OFF = OFFSET;
@@ -42,6 +45,10 @@ static_assert(Lat<FLOW>::opp(1) == 3 && Lat<FLOW>::opp(2) == 4 && Lat<FLOW>::opp
                   Lat<FLOW>::opp(6) == 8 && Lat<FLOW>::opp(8) == 6,
               "D2Q9 opposite table");
 static_assert(Lat<SWIRL>::opp(1) == 3 && Lat<SWIRL>::opp(4) == 2, "D2Q5 opposite table");
+static_assert(Lat<FLOW>::reflx(Lat<FLOW>::refl(5)) == Lat<FLOW>::opp(5) &&
+                  Lat<FLOW>::reflx(Lat<FLOW>::refl(8)) == Lat<FLOW>::opp(8) &&
+                  Lat<FLOW>::ex(Lat<FLOW>::reflx(1)) == -1 && Lat<FLOW>::ey(Lat<FLOW>::reflx(8)) == -1,
+              "D2Q9 reflection tables");
 
 // Random words of the stochastic rounding of 16-bit stores (ignored by FP32
 // storage).  A node update's 19 stores share one multiplicative hash of the
@@ -75,10 +82,11 @@ __device__ __forceinline__ bool is_wall(int k) {
     return k == NOSLIP || k == DIRICHLET || k == OMEGA_R || k == ADIABATIC || k == VELOCITY;
 }
 
-// Normal velocity that a face imposes (VELOCITY for f: along +y on radial
-// faces, +x on axial faces), 0 for every other kind.
-__device__ __forceinline__ float face_velocity(const KParams &P, int face) {
-    return kind_of(P, face, FLOW) == VELOCITY ? val_of<FLOW>(P, face) : 0.f;
+// Normal velocity that a face imposes where a link crosses it at c2
+// (VELOCITY for f: along +y on radial faces, +x on axial faces), 0 for
+// every other kind.
+__device__ __forceinline__ float face_velocity(const KParams &P, int face, int c2) {
+    return kind_at(P, face, FLOW, c2) == VELOCITY ? val_at<FLOW>(P, face, c2, 0.f) : 0.f;
 }
 
 // Moving-wall bounce-back for f: the population q that comes back off a
@@ -86,31 +94,29 @@ __device__ __forceinline__ float face_velocity(const KParams &P, int face) {
 // c_s^2 = 6 w_q (e_q . u_w) with rho_0 = 1 (shifted storage subtracts the
 // same w_q on both sides).  Lattice weights 4/9, 1/9, 1/36.
 template <int Q>
-__device__ __forceinline__ float moving_wall(const KParams &P, int face) {
+__device__ __forceinline__ float moving_wall(const KParams &P, int face, int c2) {
     using L = Lat<FLOW>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
     constexpr float w = (ex == 0 && ey == 0) ? 4.f / 9.f : ((ex == 0 || ey == 0) ? 1.f / 9.f : 1.f / 36.f);
     const float e_n = (float)(face <= R_OUT ? ey : ex);
-    return 6.f * w * e_n * val_of<FLOW>(P, face);
+    return 6.f * w * e_n * val_at<FLOW>(P, face, c2, 0.f);
 }
 
 // Unshifted wall value of g or h (u_theta,w or T_w) for the advective part
-// of the anti-bounce-back at a wall the fluid crosses.
+// of the anti-bounce-back at a wall the fluid crosses; ym is the radius
+// where the link crosses the wall, c2 twice its column.
 template <int FLD>
-__device__ __forceinline__ float wall_raw(const KParams &P, int face, float ym) {
-    const int k = kind_of(P, face, FLD);
-    const float v = val_of<FLD>(P, face);
+__device__ __forceinline__ float wall_raw(const KParams &P, int face, int c2, float ym) {
+    const int k = kind_at(P, face, FLD, c2);
+    const float v = val_at<FLD>(P, face, c2, ym);
     return k == DIRICHLET ? v : (k == OMEGA_R ? v * ym : 0.f);
 }
 
 // Value that the advection-diffusion wall rule imposes (psi_w = u_theta,w
-// with rho_0 = 1, or T_w - T_ref in shifted storage); ym is the radius where
-// the link crosses the wall.
+// with rho_0 = 1, or T_w - T_ref in shifted storage).
 template <int FLD>
-__device__ __forceinline__ float wall_value(const KParams &P, int face, float ym) {
-    const int k = kind_of(P, face, FLD);
-    const float v = val_of<FLD>(P, face);
-    float s = k == DIRICHLET ? v : (k == OMEGA_R ? v * ym : 0.f);
+__device__ __forceinline__ float wall_value(const KParams &P, int face, int c2, float ym) {
+    float s = wall_raw<FLD>(P, face, c2, ym);
     if (FLD == THERMAL) s -= P.Tref;
     return s;
 }
@@ -141,32 +147,37 @@ struct GlobalPops {
 // solid wall (radial faces first) -> half-way bounce-back for f and for zero
 // flux, anti-bounce-back -v + 2 w s_w (w = 1/6) for an imposed u_theta or T;
 // then the axis -> specular reflection from the node shifted by e_x, with a
-// sign change for g (u_theta is odd); then the periodic image along z.
+// sign change for g (u_theta is odd); then a free surface on an axial face
+// (SLIP, f only) -> specular reflection from the node shifted by e_y (after
+// the axis reflection where a link crosses both); then the periodic image
+// along z.  An axial face split in two parts gives a link the rule of the
+// part where it crosses the face, at twice the column c2 = 2 j - e_y.
 // AA selects the slot convention of the odd phase of the in-place layout.
 template <bool AA, int FLD, int Q, class Src>
 __device__ __forceinline__ float pull_edge(const KParams &P, const Src &src, int i, int j) {
     using L = Lat<FLD>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
-    const int si = i - ex;
+    int si = i - ex;
     int sj = j - ey;
+    const int c2 = 2 * j - ey;
     const int fy = sj < 0 ? R_IN : (sj >= P.Nr ? R_OUT : -1);
     const int fx = si < 0 ? Z_LO : (si >= P.Nz ? Z_HI : -1);
     int wall = -1;
     if (fy >= 0 && is_wall(kind_of(P, fy, FLD))) wall = fy;
-    else if (fx >= 0 && is_wall(kind_of(P, fx, FLD))) wall = fx;
+    else if (fx >= 0 && is_wall(kind_at(P, fx, FLD, c2))) wall = fx;
     if (wall >= 0) {
         // f*_{opp Q}(i, j): AB keeps it in plane opp Q, the even AA phase put
         // it into plane Q.
         constexpr int slot = AA ? Q : L::opp(Q);
         const float v = src(L::OFF + slot, i, j);
-        const bool moving = kind_of(P, wall, FLOW) == VELOCITY;
-        if (FLD == FLOW) return moving ? v + moving_wall<Q>(P, wall) : v;
-        if (kind_of(P, wall, FLD) == ADIABATIC) return v;
+        const bool moving = kind_at(P, wall, FLOW, c2) == VELOCITY;
+        if (FLD == FLOW) return moving ? v + moving_wall<Q>(P, wall, c2) : v;
+        if (kind_at(P, wall, FLD, c2) == ADIABATIC) return v;
         const float ym = P.r0 + (float)j + 0.5f - 0.5f * (float)ey;
-        const float r = -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
+        const float r = -v + (1.f / 3.f) * wall_value<FLD>(P, wall, c2, ym);
         if (!moving) return r;
-        const float un = val_of<FLOW>(P, wall);
-        return r + un * un * wall_raw<FLD>(P, wall, ym);
+        const float un = val_at<FLOW>(P, wall, c2, 0.f);
+        return r + un * un * wall_raw<FLD>(P, wall, c2, ym);
     }
     float sign = 1.f;
     int qs = Q;
@@ -174,6 +185,10 @@ __device__ __forceinline__ float pull_edge(const KParams &P, const Src &src, int
         qs = L::refl(Q);
         sj = j;
         if (FLD == SWIRL) sign = -1.f;
+    }
+    if (FLD == FLOW && fx >= 0 && kind_at(P, fx, FLOW, c2) == SLIP) {
+        qs = Lat<FLOW>::reflx(qs);
+        si = i;
     }
     const int slot = AA ? L::opp(qs) : qs;
     return sign * src(L::OFF + slot, si, sj);  // a z row beyond a periodic face: its image
@@ -226,34 +241,50 @@ __device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, 
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
     int ti = i + ex;
     const int tj = j + ey;
+    // the link crosses an axial face at twice the column 2 j + e_y (the
+    // receiving node's 2 j' - e_y of the pull form)
+    const int c2 = 2 * j + ey;
     const int fy = tj < 0 ? R_IN : (tj >= P.Nr ? R_OUT : -1);
     const int fx = ti < 0 ? Z_LO : (ti >= P.Nz ? Z_HI : -1);
     int wall = -1;
     if (fy >= 0 && is_wall(kind_of(P, fy, FLD))) wall = fy;
-    else if (fx >= 0 && is_wall(kind_of(P, fx, FLD))) wall = fx;
+    else if (fx >= 0 && is_wall(kind_at(P, fx, FLD, c2))) wall = fx;
     if (wall >= 0) {
         // it comes back to (i, j) as population opp Q
         float w = v;
-        const bool moving = kind_of(P, wall, FLOW) == VELOCITY;
+        const bool moving = kind_at(P, wall, FLOW, c2) == VELOCITY;
         if (FLD == FLOW) {
-            if (moving) w = v + moving_wall<L::opp(Q)>(P, wall);
-        } else if (kind_of(P, wall, FLD) != ADIABATIC) {
+            if (moving) w = v + moving_wall<L::opp(Q)>(P, wall, c2);
+        } else if (kind_at(P, wall, FLD, c2) != ADIABATIC) {
             const float ym = P.r0 + (float)j + 0.5f + 0.5f * (float)ey;
-            w = -v + (1.f / 3.f) * wall_value<FLD>(P, wall, ym);
+            w = -v + (1.f / 3.f) * wall_value<FLD>(P, wall, c2, ym);
             if (moving) {
-                const float un = val_of<FLOW>(P, wall);
-                w = w + un * un * wall_raw<FLD>(P, wall, ym);
+                const float un = val_at<FLOW>(P, wall, c2, 0.f);
+                w = w + un * un * wall_raw<FLD>(P, wall, c2, ym);
             }
         }
         Conv<S>::st(A + (L::OFF + L::opp(Q)) * P.plane + (long long)i * P.pitch + j, w,
                     slot_word(w0, L::OFF + Q));
         return;
     }
+    const bool slip = FLD == FLOW && fx >= 0 && kind_at(P, fx, FLOW, c2) == SLIP;
     if (fy >= 0) {  // axis: arrives at (i + e_x, j) with e_y reversed
-        if (ti < 0) ti += P.Nz;
-        else if (ti >= P.Nz) ti -= P.Nz;
-        Conv<S>::st(A + (L::OFF + L::refl(Q)) * P.plane + (long long)ti * P.pitch + j,
+        int q = L::refl(Q);
+        if (slip) {  // and off the free surface: at (i, j), both reversed
+            ti = i;
+            q = Lat<FLOW>::reflx(q);
+        } else if (ti < 0) {
+            ti += P.Nz;
+        } else if (ti >= P.Nz) {
+            ti -= P.Nz;
+        }
+        Conv<S>::st(A + (L::OFF + q) * P.plane + (long long)ti * P.pitch + j,
                     FLD == SWIRL ? -v : v, slot_word(w0, L::OFF + Q));
+        return;
+    }
+    if (slip) {  // free surface: arrives at (i, j + e_y) with e_x reversed
+        Conv<S>::st(A + (L::OFF + Lat<FLOW>::reflx(Q)) * P.plane + (long long)i * P.pitch + tj, v,
+                    slot_word(w0, L::OFF + Q));
         return;
     }
     ti += ti < 0 ? P.Nz : -P.Nz;  // periodic
@@ -281,7 +312,8 @@ __device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float
 // beyond a periodic face; beyond a wall or the axis the value is a ghost
 // mirrored through the half-way wall: -q for u_x, u_y at a no-slip wall,
 // 2 q_w - q for an imposed u_theta or T, q for zero flux; q (u_x, T) or -q
-// (u_y, u_theta) at the axis, with q = get(v, 0, 0) the node's own value.
+// (u_y, u_theta) at the axis; -q for u_x and q for u_y at a free surface,
+// with q = get(v, 0, 0) the node's own value.
 template <class Get>
 __device__ __forceinline__ float field_at(const KParams &P, const Get &get, int v, int i, int j,
                                           int di, int dj) {
@@ -289,18 +321,20 @@ __device__ __forceinline__ float field_at(const KParams &P, const Get &get, int 
     if ((unsigned)ni < (unsigned)P.Nz && (unsigned)nj < (unsigned)P.Nr) return get(v, di, dj);
     const int face = nj < 0 ? R_IN : (nj >= P.Nr ? R_OUT : (ni < 0 ? Z_LO : Z_HI));
     const int fld = v <= 1 ? FLOW : (v == 2 ? SWIRL : THERMAL);
-    const int k = kind_of(P, face, fld);
+    const int c2 = 2 * j;  // an axial neighbour: the node's own column
+    const int k = kind_at(P, face, fld, c2);
     if (k == PERIODIC || k == HALO) return get(v, di, dj);
     const float q1 = get(v, 0, 0);
     if (k == MIRROR) return (v == 0 || v == 3) ? q1 : -q1;
     if (k == ADIABATIC) return q1;
+    if (k == SLIP) return v == 0 ? -q1 : q1;  // free surface: u_x = 0, d_x u_y = 0
     if (v <= 1) {
         // the velocity component normal to a wall that imposes one: 2 u_w - q
         const int normal = face <= R_OUT ? 1 : 0;
-        return v == normal ? 2.f * face_velocity(P, face) - q1 : -q1;
+        return v == normal ? 2.f * face_velocity(P, face, c2) - q1 : -q1;
     }
     const float yw = P.r0 + (float)j + 0.5f + 0.5f * (float)dj;
-    const float s = v == 2 ? wall_value<SWIRL>(P, face, yw) : wall_value<THERMAL>(P, face, yw);
+    const float s = v == 2 ? wall_value<SWIRL>(P, face, c2, yw) : wall_value<THERMAL>(P, face, c2, yw);
     return 2.f * s - q1;
 }
 

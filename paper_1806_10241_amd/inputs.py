@@ -32,7 +32,7 @@ import numpy as np
 # Faces, distributions and boundary kinds (numbering of the C interface).
 R_IN, R_OUT, Z_LO, Z_HI = 0, 1, 2, 3
 FLOW, SWIRL, THERMAL = 0, 1, 2
-NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, VELOCITY = 0, 1, 2, 3, 4, 5, 7
+NOSLIP, PERIODIC, MIRROR, DIRICHLET, OMEGA_R, ADIABATIC, VELOCITY, SLIP = 0, 1, 2, 3, 4, 5, 7, 8
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -271,6 +271,54 @@ def mixed_convection_annulus(Nr: int = 40, slenderness: float = 10.0, Re: float 
                 nu=nu, alpha=alpha, Pr=Pr, Ra=gbeta * D ** 3 / (nu * alpha), Re=Re,
                 sigma=sigma, g_axial=0.0, T0=0.5, omega3=1.0, bc=bc, T_ref=0.5, seed=seed,
                 fields=_perturbed_T(seed, Nz, Nr))
+
+
+def czochralski_melt(N: int = 40, Re_x: float = 100.0, Re_c: float = -25.0, Pr: float = 0.05,
+                     beta: float = 0.4, aspect: float = 1.0, Gr: float = 0.0, u_max: float = 0.05,
+                     seed: int = 24) -> dict:
+    """Melt in a turning crucible under a turning crystal (Wheeler's
+    Czochralski problem, Section 3.6).
+
+    Crucible radius R_c = N, melt depth H = aspect * R_c, crystal radius
+    R_x = beta * R_c (a whole number of nodes).  The crucible (side wall and
+    bottom) turns at Omega_c = Re_c nu / R_c^2 and the crystal at Omega_x =
+    Re_x nu / R_c^2 (opposite senses for Re_c < 0): both Reynolds numbers on
+    the crucible radius, the length scale of the problem's other groups;
+    nu is set so that the faster of the two rims moves at u_max.  Side wall
+    T = 1, crystal T = 0, the free surface between them (R_x < r < R_c,
+    flat, no shear) T linear in r from 0 to 1, adiabatic bottom.  Pr =
+    nu / alpha, Gr = g beta (T_H - T_L) R_c^3 / nu^2 (Section 3.6 gives none:
+    0 by default, where T is carried by the flow but does not drive it).
+    The fluid starts at rest at T = 1/2 plus seeded noise of amplitude
+    1e-4."""
+    Nz = int(round(aspect * N))
+    s = int(round(beta * N))
+    Rx, Rc = float(s), float(N)
+    # rim speeds Omega R = Re nu R / R_c^2; the faster one is u_max
+    nu = u_max * Rc ** 2 / max(abs(Re_x) * Rx, abs(Re_c) * Rc)
+    alpha = nu / Pr
+    Om_x, Om_c = Re_x * nu / Rc ** 2, Re_c * nu / Rc ** 2
+    bc = {}
+    _axis(bc)
+    bc[(R_OUT, FLOW)] = (NOSLIP, 0.0)
+    bc[(R_OUT, SWIRL)] = (OMEGA_R, Om_c)
+    bc[(R_OUT, THERMAL)] = (DIRICHLET, 1.0)
+    bc[(Z_LO, FLOW)] = (NOSLIP, 0.0)
+    bc[(Z_LO, SWIRL)] = (OMEGA_R, Om_c)
+    bc[(Z_LO, THERMAL)] = (ADIABATIC, 0.0)
+    # the top: the crystal for r < R_x, the free surface beyond
+    bc[(Z_HI, FLOW)] = (NOSLIP, 0.0)
+    bc[(Z_HI, SWIRL)] = (OMEGA_R, Om_x)
+    bc[(Z_HI, THERMAL)] = (DIRICHLET, 0.0)
+    b = Rx / Rc
+    outer = {(Z_HI, FLOW): (SLIP, 0.0), (Z_HI, SWIRL): (ADIABATIC, 0.0),
+             # T = (r / R_c - beta) / (1 - beta) = value + slope * r
+             (Z_HI, THERMAL): (DIRICHLET, -b / (1.0 - b), 1.0 / ((1.0 - b) * Rc))}
+    return dict(name="czochralski_melt", Nr=N, Nz=Nz, cylinder=1, r_inner=0.0, nu=nu,
+                alpha=alpha, Pr=Pr, Ra=Gr * Pr, Gr=Gr, Re_x=Re_x, Re_c=Re_c, Omega_x=Om_x,
+                Omega_c=Om_c,
+                R_x=Rx, R_c=Rc, g_axial=0.0, T0=0.5, omega3=1.0, bc=bc, split={Z_HI: s},
+                outer=outer, T_ref=0.5, seed=seed, fields=_perturbed_T(seed, Nz, N))
 
 
 def batched_annuli(n: int = 256, seed: int = 4):
