@@ -330,9 +330,14 @@ int axlb_halo_import(axlb_lattice *lat, int face, const void *device_src);
  * before the next run starts, two runs at a time on two streams (together
  * below the 256 MB Infinity Cache); after axlb_batch_step every member has
  * advanced by the same count either way.
- * Members must share device
- * and storage, use the AA layout and belong to no other batch; their
- * boundary rules are locked.  While batched, a member runs on the batch's
+ * A batch of AXLB_LAYOUT_AB2 members instead advances every member by two
+ * steps per launch (the two-step kernel over a work-list of (member, tile)
+ * entries, all members in one launch, 100-step bundles as graphs of 50
+ * launches): the state crosses HBM once per two steps, which is what a
+ * batch whose states exceed the Infinity Cache gains most from.  An odd
+ * step count ends with one single step of each member.
+ * Members must share device, storage and layout (AA or AB2) and belong to
+ * no other batch; their boundary rules are locked.  While batched, a member runs on the batch's
  * stream: axlb_get_moments, axlb_nusselt, axlb_residual and axlb_save work
  * on it as usual, whereas axlb_step, axlb_set_fields, axlb_load,
  * axlb_set_tile, axlb_autotune and axlb_destroy refuse (AXLB_ESTATE).  A
@@ -348,14 +353,16 @@ int axlb_batch_step(axlb_batch *b, long n);
 int axlb_batch_sync(axlb_batch *b);
 /* Tile shape (as axlb_tile_shape) and schedule: blocks = 0 launches one
  * workgroup per work-list entry, blocks > 0 that many persistent workgroups
- * that loop over the entries. */
+ * that loop over the entries.  AA members only (AXLB_EINVAL for AB2, whose
+ * batch has one schedule). */
 int axlb_batch_set_schedule(axlb_batch *b, int tile, int blocks);
 int axlb_batch_get_schedule(const axlb_batch *b, int *tile, int *blocks);
 /* Times every tile shape with each of the AXLB_NSCHEDULES schedules (one
  * workgroup per entry, 4, 8 and 16 persistent workgroups per compute unit)
  * for steps_per_trial steps (group by group, as the bundles of
  * axlb_batch_step run), restores the members' state, keeps the fastest.
- * ms_per_step[AXLB_NTILES * AXLB_NSCHEDULES] may be NULL. */
+ * ms_per_step[AXLB_NTILES * AXLB_NSCHEDULES] may be NULL.  A batch of AB2
+ * members has nothing to choose: it returns at once (times 0). */
 int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
                         int *best_tile, int *best_blocks);
 void axlb_batch_destroy(axlb_batch *b);

@@ -123,9 +123,15 @@ struct axlb_batch {
     std::vector<axlb_lattice *> members;
     std::vector<hipStream_t> member_streams;
     int storage = 0;
+    int layout = AXLB_LAYOUT_AA;
     int tile = 0;
     int blocks = 0;  // 0: one block per work-list entry; else persistent blocks
     InstDesc *d_desc = nullptr;
+    // two-buffer members (AXLB_LAYOUT_AB2): two steps per launch; a member
+    // reads buffer pair cur0 ^ phase, and phase flips with every launch
+    TwoDesc *d_two = nullptr;
+    int2 *d_two_tiles = nullptr;
+    int phase = 0;
     int *d_tiles = nullptr;
     int ntiles = 0;
     // work-list ranges of consecutive members whose state fits the
@@ -160,8 +166,55 @@ static void drop_batch_graphs(axlb_batch *b) {
         }
 }
 
+// Descriptors and work-list of a batch of two-buffer members: every tile
+// of the two-step kernel of every member, in one group, in member order
+// (which the kernel cuts into its 8 XCD chunks).  Listing each chunk's rim
+// tiles first, as the single-lattice launch does, measured slower here
+// (21.2k against 24.8k MLUPS for the 256 uneven annuli): a member's rim
+// and inner tiles then run apart and lose the L2 reuse of their shared
+// rows, and small members are mostly rim.
+static int build_worklist_two(axlb_batch *b) {
+    int tw, th;
+    two_tile_shape(&tw, &th);
+    std::vector<TwoDesc> desc(b->members.size());
+    std::vector<int2> tiles;
+    for (size_t m = 0; m < b->members.size(); ++m) {
+        axlb_lattice *L = b->members[m];
+        TwoDesc &d = desc[m];
+        std::memset(&d, 0, sizeof(d));
+        d.P = L->P;
+        for (int c = 0; c < 2; ++c) {
+            d.src[c] = L->pop[c];
+            d.lag[c] = L->lag[c];
+            d.pl[c] = step_planes(L->P, L->storage, MODE_AB, L->pop[c], L->pop[c ^ 1], L->lag[c],
+                                  L->lag[c ^ 1]);
+        }
+        d.cur0 = L->cur ^ b->phase;
+        d.gx = (L->Nr + tw - 1) / tw;
+        const int gy = (L->Nz + th - 1) / th;
+        for (int t = 0; t < d.gx * gy; ++t) tiles.push_back(make_int2((int)m, t));
+    }
+    const int n = (int)tiles.size();
+    b->group.assign({0, n});
+    if (b->d_two) (void)hipFree(b->d_two);
+    if (b->d_two_tiles) (void)hipFree(b->d_two_tiles);
+    b->d_two = nullptr;
+    b->d_two_tiles = nullptr;
+    BHIP(b, hipMalloc((void **)&b->d_two, desc.size() * sizeof(TwoDesc)));
+    BHIP(b, hipMalloc((void **)&b->d_two_tiles, tiles.size() * sizeof(int2)));
+    BHIP(b, hipMemcpyAsync(b->d_two, desc.data(), desc.size() * sizeof(TwoDesc),
+                           hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_two_tiles, tiles.data(), tiles.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    b->ntiles = n;
+    drop_batch_graphs(b);
+    return AXLB_OK;
+}
+
 // Descriptors and work-list for the current tile shape.
 static int build_worklist(axlb_batch *b) {
+    if (b->layout == AXLB_LAYOUT_AB2) return build_worklist_two(b);
     int bx, by;
     tile_shape(b->tile, &bx, &by);
     std::vector<InstDesc> desc(b->members.size());
@@ -229,6 +282,71 @@ static void advance_members(axlb_batch *b, long n) {
     for (axlb_lattice *L : b->members) L->steps += n;
 }
 
+// One two-step launch of every member of a two-buffer batch.
+static int two_launch(axlb_batch *b, int phase) {
+    const hipError_t e = launch_step_two_batch(b->storage, b->d_two, b->d_two_tiles, 0,
+                                               b->ntiles, phase, b->stream);
+    if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+    return AXLB_OK;
+}
+
+// After `launches` two-step launches: two steps each, one buffer flip each.
+static void advance_two(axlb_batch *b, long launches) {
+    advance_members(b, 2 * launches);
+    if (launches & 1) {
+        b->phase ^= 1;
+        for (axlb_lattice *L : b->members) L->cur ^= 1;
+    }
+}
+
+// n steps of a two-buffer batch: 100-step bundles as graphs of 50 launches
+// (keyed by the phase they start from), pairs of steps as plain launches,
+// and a last odd step as one single step of each member (which flips its
+// buffers as a launch does).
+static int batch_step_two(axlb_batch *b, long n) {
+    while (n > 0) {
+        if (n >= BUNDLE) {
+            const int k = b->phase;
+            if (!b->graph[k]) {
+                BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                int rc = AXLB_OK;
+                for (long s = 0; s < BUNDLE / 2 && rc == AXLB_OK; ++s)
+                    rc = two_launch(b, (int)((k + s) & 1));
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(b->stream, &g);
+                if (rc != AXLB_OK) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return rc;
+                }
+                if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, "batch graph capture failed");
+                e = hipGraphInstantiate(&b->graph[k], g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    b->graph[k] = nullptr;
+                    return bfail(b, AXLB_EDEVICE, "batch graph instantiate failed");
+                }
+            }
+            BHIP(b, hipGraphLaunch(b->graph[k], b->stream));
+            advance_two(b, BUNDLE / 2);
+            n -= BUNDLE;
+        } else if (n >= 2) {
+            const int rc = two_launch(b, b->phase);
+            if (rc) return rc;
+            advance_two(b, 1);
+            n -= 2;
+        } else {
+            for (axlb_lattice *L : b->members) {
+                const int rc = lattice_step_once(L);
+                if (rc) return bfail(b, rc, L->err);
+            }
+            b->steps += 1;
+            b->phase ^= 1;
+            n -= 1;
+        }
+    }
+    return AXLB_OK;
+}
+
 extern "C" {
 
 int axlb_batch_create(axlb_lattice *const *lats, int n, axlb_batch **out) {
@@ -240,7 +358,9 @@ int axlb_batch_create(axlb_lattice *const *lats, int n, axlb_batch **out) {
         axlb_lattice *L = lats[m];
         if (!L) return bfail(nullptr, AXLB_EINVAL, "NULL member");
         if (L->device != dev) return bfail(nullptr, AXLB_EINVAL, "members on different devices");
-        if (L->layout != AXLB_LAYOUT_AA) return bfail(nullptr, AXLB_EINVAL, "batches need the AA layout");
+        if (L->layout != AXLB_LAYOUT_AA && L->layout != AXLB_LAYOUT_AB2)
+            return bfail(nullptr, AXLB_EINVAL, "batches need the AA or the AB2 layout");
+        if (L->layout != lats[0]->layout) return bfail(nullptr, AXLB_EINVAL, "mixed layouts in a batch");
         if (L->storage != lats[0]->storage) return bfail(nullptr, AXLB_EINVAL, "mixed storage in a batch");
         if (L->batched) return bfail(nullptr, AXLB_ESTATE, "lattice already in a batch");
         for (int k = 0; k < m; ++k)
@@ -250,6 +370,7 @@ int axlb_batch_create(axlb_lattice *const *lats, int n, axlb_batch **out) {
     if (!b) return bfail(nullptr, AXLB_ENOMEM, "host allocation failed");
     b->device = dev;
     b->storage = lats[0]->storage;
+    b->layout = lats[0]->layout;
     if (hipSetDevice(dev) != hipSuccess ||
         hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
@@ -299,6 +420,8 @@ int axlb_batch_size(const axlb_batch *b, int *members, long long *nodes) {
 int axlb_batch_set_schedule(axlb_batch *b, int tile, int blocks) {
     if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
     if (tile < 0 || tile >= tile_count() || blocks < 0) return bfail(b, AXLB_EINVAL, "bad schedule");
+    if (b->layout == AXLB_LAYOUT_AB2)
+        return bfail(b, AXLB_EINVAL, "a batch of AB2 members has one schedule");
     BHIP(b, hipSetDevice(b->device));
     BHIP(b, hipStreamSynchronize(b->stream));
     const bool rebuild = tile != b->tile;
@@ -319,6 +442,7 @@ int axlb_batch_step(axlb_batch *b, long n) {
     if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
     if (n < 0) return bfail(b, AXLB_EINVAL, "negative step count");
     BHIP(b, hipSetDevice(b->device));
+    if (b->layout == AXLB_LAYOUT_AB2) return batch_step_two(b, n);
     while (n > 0) {
         if (n >= BUNDLE) {
             const int k = (int)(b->steps & 1);
@@ -377,6 +501,14 @@ int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
     if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
     if (steps_per_trial < 2) return bfail(b, AXLB_EINVAL, "steps_per_trial must be >= 2");
     BHIP(b, hipSetDevice(b->device));
+    if (b->layout == AXLB_LAYOUT_AB2) {
+        // one schedule: nothing to choose
+        if (ms_per_step)
+            for (int k = 0; k < tile_count() * AXLB_NSCHEDULES; ++k) ms_per_step[k] = 0.0;
+        if (best_tile) *best_tile = b->tile;
+        if (best_blocks) *best_blocks = b->blocks;
+        return AXLB_OK;
+    }
     int dev_cu = 0;
     BHIP(b, hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, b->device));
     const int sched[AXLB_NSCHEDULES] = {0, 4 * dev_cu, 8 * dev_cu, 16 * dev_cu};
@@ -458,6 +590,8 @@ void axlb_batch_destroy(axlb_batch *b) {
         b->members[m]->batched = false;
     }
     if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_two) (void)hipFree(b->d_two);
+    if (b->d_two_tiles) (void)hipFree(b->d_two_tiles);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
     if (b->join) (void)hipEventDestroy(b->join);
     if (b->fork) (void)hipEventDestroy(b->fork);

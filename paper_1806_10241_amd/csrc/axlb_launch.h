@@ -45,6 +45,21 @@ hipError_t launch_fields_current(const KParams &P, int storage, const void *src,
 // the state before step t, dst/Mnext receive it after step t + 1.
 hipError_t launch_step_two(const KParams &P, int storage, const void *src, void *dst,
                            const char *Mprev, char *Mnext, hipStream_t st);
+// A member of a batch of two-buffer lattices, for the two-step launch:
+// buffer pair c (0 or 1) is read when the member's current pair is c.
+struct TwoDesc {
+    KParams P;
+    const void *src[2];    // population buffer read from pair c
+    const char *lag[2];    // lagged fields read from pair c
+    Planes pl[2];          // plane addresses of a two-step launch from pair c
+    int cur0;              // the member's pair at batch creation
+    int gx;                // tiles along r
+};
+// Interior tile of the two-step kernel (nodes along r, along z).
+void two_tile_shape(int *tw, int *th);
+// Work-list entries (member, tile index within the member).
+hipError_t launch_step_two_batch(int storage, const TwoDesc *D, const int2 *tiles, int t0,
+                                 int ntiles, int phase, hipStream_t st);
 hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
                        char *M, hipStream_t st);
 hipError_t launch_residual(const double *fld, const double *snap, long long N, double *part,

@@ -70,20 +70,18 @@ __device__ __forceinline__ void pull_lds_all(const S (&A)[NPOP][H][W], int a, in
     h[4] = pull_lds<S, THERMAL, 4>(A, a, b);
 }
 
+// Two steps of the tile whose first node is (i0, j0), with the workgroup's
+// LDS block.  A: plane addresses of the launch (populations of src, the
+// lagged fields of Mprev, and the write planes of dst and Mnext); src and
+// Mprev also serve the general path of the lattice's edge cells.  Every
+// thread reaches the barrier and the end (no early return), so a workgroup
+// may call it for one tile after another.
 template <class S>
-__global__ void __launch_bounds__(TWO_CW *TWO_CH) k_step_two(const KParams P, const Planes A,
-                                                              const S *src, S *dst,
-                                                              const char *__restrict__ Mprev,
-                                                              char *__restrict__ Mnext) {
+__device__ __forceinline__ void step_two_tile(const KParams &P, const Planes &A, const S *src,
+                                              const char *__restrict__ Mprev, int i0, int j0,
+                                              S (&pop)[NPOP][TWO_CH][TWO_CW],
+                                              float (&lag)[NLAG][TWO_CH][TWO_CW]) {
     constexpr int W = TWO_CW, H = TWO_CH;
-    __shared__ S pop[NPOP][H][W];
-    __shared__ float lag[NLAG][H][W];
-    // tile of this workgroup, XCD-banded as tile_of deals them
-    const int gx = (P.Nr + TWO_TW - 1) / TWO_TW;
-    const int nb = gx * ((P.Nz + TWO_TH - 1) / TWO_TH);
-    const int bid = (int)blockIdx.x, xcd = bid & 7, k = bid >> 3, q = nb >> 3, r = nb & 7;
-    const int t = xcd * q + (xcd < r ? xcd : r) + k;
-    const int i0 = (t / gx) * TWO_TH, j0 = (t % gx) * TWO_TW;
     const int a = (int)threadIdx.x / W, b = (int)threadIdx.x % W;
 
     // step t for this thread's cell
@@ -124,31 +122,124 @@ __global__ void __launch_bounds__(TWO_CW *TWO_CH) k_step_two(const KParams P, co
     __syncthreads();
 
     // step t + 1 for the tile's own nodes, from LDS
-    if (a < 1 || a > TWO_TH || b < 1 || b > TWO_TW) return;
     const int i = i0 - 1 + a, j = j0 - 1 + b;
-    if (i >= P.Nz || j >= P.Nr) return;
-    float f[9], g[5], h[5], d[5];
-    if (interior_node(P, i, j)) {
-        pull_lds_all<S>(pop, a, b, f, g, h);
-        d[0] = 0.5f * (lag[1][a + 1][b] - lag[1][a - 1][b]);
-        d[1] = 0.5f * (lag[0][a][b + 1] - lag[0][a][b - 1]);
-        d[2] = 0.5f * (lag[1][a][b + 1] - lag[1][a][b - 1]);
-        d[3] = 0.5f * (lag[2][a][b + 1] - lag[2][a][b - 1]);
-        d[4] = 0.5f * (lag[3][a][b + 1] - lag[3][a][b - 1]);
-    } else {
-        pull_all<false>(P, TilePops<S, H, W>{pop, i0, j0}, i, j, f, g, h);
-        differences(P, TileSource<H, W>{lag, a, b}, i, j, d);
+    if (a >= 1 && a <= TWO_TH && b >= 1 && b <= TWO_TW && i < P.Nz && j < P.Nr) {
+        float f[9], g[5], h[5], d[5];
+        if (interior_node(P, i, j)) {
+            pull_lds_all<S>(pop, a, b, f, g, h);
+            d[0] = 0.5f * (lag[1][a + 1][b] - lag[1][a - 1][b]);
+            d[1] = 0.5f * (lag[0][a][b + 1] - lag[0][a][b - 1]);
+            d[2] = 0.5f * (lag[1][a][b + 1] - lag[1][a][b - 1]);
+            d[3] = 0.5f * (lag[2][a][b + 1] - lag[2][a][b - 1]);
+            d[4] = 0.5f * (lag[3][a][b + 1] - lag[3][a][b - 1]);
+        } else {
+            pull_all<false>(P, TilePops<S, H, W>{pop, i0, j0}, i, j, f, g, h);
+            differences(P, TileSource<H, W>{lag, a, b}, i, j, d);
+        }
+        const Half Hs = relax_node(P, j, f, g, h, d);
+        using F = LagFmt<S>;
+        const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+        const unsigned so = local_offset(n * (unsigned)sizeof(S)), sov = local_offset(n * F::VB);
+        const unsigned so4 = local_offset(n * 4u);
+        scatter_planes<S>(A, so, i, j, f, g, h);
+        gstore(A.lwr[0], sov, F::enc(Hs.ux));
+        gstore(A.lwr[1], sov, F::enc(Hs.uy));
+        gstore(A.lwr[2], sov, F::enc(Hs.psi * Hs.irho));
+        gstore(A.lwr[3], so4, Hs.dphi);
     }
-    const Half Hs = relax_node(P, j, f, g, h, d);
-    using F = LagFmt<S>;
-    const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
-    const unsigned so = local_offset(n * (unsigned)sizeof(S)), sov = local_offset(n * F::VB);
-    const unsigned so4 = local_offset(n * 4u);
-    scatter_planes<S>(A, so, i, j, f, g, h);
-    gstore(A.lwr[0], sov, F::enc(Hs.ux));
-    gstore(A.lwr[1], sov, F::enc(Hs.uy));
-    gstore(A.lwr[2], sov, F::enc(Hs.psi * Hs.irho));
-    gstore(A.lwr[3], so4, Hs.dphi);
+}
+
+// Workgroups of a two-step launch over a gx x gy grid of tiles: the tiles
+// on the rim of the grid (which hold the lattice's edge nodes and run the
+// general boundary code) come first, padded to a multiple of 8 so that the
+// inner tiles after them start on XCD 0; the inner tiles are dealt to the
+// XCDs in 8 contiguous bands, as tile_of deals a single-step grid.  With
+// the boundary code confined to the first workgroups, the instruction
+// cache of every compute unit holds only the inner path for the rest of
+// the launch: at 1024 x 2048 (FP32) the two steps take 104.4 us instead of
+// 113.0 us in one banded order.
+__host__ __device__ inline int two_rim_tiles(int gx, int gy) {
+    return (gx <= 2 || gy <= 2) ? 0 : 2 * gx + 2 * (gy - 2);
+}
+__host__ __device__ inline int two_grid_blocks(int gx, int gy) {
+    const int nE = two_rim_tiles(gx, gy);
+    return nE == 0 ? gx * gy : ((nE + 7) & ~7) + (gx - 2) * (gy - 2);
+}
+// Tile (tx, ty) of workgroup bid; false for a padding workgroup.
+__device__ inline bool two_tile_of(int gx, int gy, int bid, int &tx, int &ty) {
+    const int nE = two_rim_tiles(gx, gy);
+    if (nE == 0) {  // small grids: every tile is on the rim; XCD bands
+        const int nb = gx * gy, xcd = bid & 7, k = bid >> 3, q = nb >> 3, r = nb & 7;
+        const int t = xcd * q + (xcd < r ? xcd : r) + k;
+        tx = t % gx;
+        ty = t / gx;
+        return true;
+    }
+    const int nEp = (nE + 7) & ~7;
+    if (bid < nEp) {
+        if (bid >= nE) return false;
+        if (bid < 2 * gx) {  // first and last row of tiles
+            tx = bid % gx;
+            ty = bid < gx ? 0 : gy - 1;
+        } else {  // first and last column, between them
+            const int e = bid - 2 * gx;
+            tx = e < gy - 2 ? 0 : gx - 1;
+            ty = 1 + (e < gy - 2 ? e : e - (gy - 2));
+        }
+        return true;
+    }
+    const int b = bid - nEp, nI = (gx - 2) * (gy - 2);
+    const int xcd = b & 7, k = b >> 3, q = nI >> 3, r = nI & 7;
+    const int t = xcd * q + (xcd < r ? xcd : r) + k;
+    tx = 1 + t % (gx - 2);
+    ty = 1 + t / (gx - 2);
+    return true;
+}
+
+template <class S>
+__global__ void __launch_bounds__(TWO_CW *TWO_CH) k_step_two(const KParams P, const Planes A,
+                                                              const S *src,
+                                                              const char *__restrict__ Mprev) {
+    __shared__ S pop[NPOP][TWO_CH][TWO_CW];
+    __shared__ float lag[NLAG][TWO_CH][TWO_CW];
+    const int gx = (P.Nr + TWO_TW - 1) / TWO_TW, gy = (P.Nz + TWO_TH - 1) / TWO_TH;
+    int tx, ty;
+    if (!two_tile_of(gx, gy, (int)blockIdx.x, tx, ty)) return;  // padding: the whole workgroup
+    step_two_tile<S>(P, A, src, Mprev, ty * TWO_TH, tx * TWO_TW, pop, lag);
+}
+
+// Two steps of many lattices (a batch of two-buffer members): one
+// workgroup per work-list entry (member, tile index within the member),
+// the entries dealt to the 8 XCDs in 8 contiguous chunks so that a
+// member's tiles share an L2.  A member reads buffer pair
+// cur0 ^ phase (its state when the batch was made, flipped once per
+// launch).
+// Six waves per SIMD (three workgroups per CU, as the LDS allows) need at
+// most 80 VGPRs; left alone the compiler takes 84 for the parameters it
+// reads from the descriptors.
+template <class S>
+__global__ void __launch_bounds__(TWO_CW *TWO_CH, 6) k_step_two_batch(const TwoDesc *__restrict__ D,
+                                                                    const int2 *__restrict__ tile_inst,
+                                                                    int t0, int ntiles, int phase) {
+    __shared__ S pop[NPOP][TWO_CH][TWO_CW];
+    __shared__ float lag[NLAG][TWO_CH][TWO_CW];
+    const int G = gridDim.x, bk = blockIdx.x;
+    const int xcd = bk & 7, k = bk >> 3;
+    // chunk sizes follow the block counts per XCD, so that with one block
+    // per entry every block takes exactly one
+    const int nbx = (G >> 3) + (xcd < (G & 7) ? 1 : 0);
+    const int q = ntiles >> 3, r = ntiles & 7;
+    const int lo = t0 + xcd * q + (xcd < r ? xcd : r);
+    const int hi = lo + q + (xcd < r ? 1 : 0);
+    for (int t = lo + k; t < hi; t += nbx) {
+        const int2 e = tile_inst[t];
+        const TwoDesc *d = D + e.x;
+        const int c = d->cur0 ^ phase;
+        const int local = e.y;
+        step_two_tile<S>(d->P, d->pl[c], static_cast<const S *>(d->src[c]), d->lag[c],
+                         (local / d->gx) * TWO_TH, (local % d->gx) * TWO_TW, pop, lag);
+        __syncthreads();  // the LDS block is refilled by the next entry
+    }
 }
 
 template <class S>
@@ -156,8 +247,26 @@ static hipError_t step_two_t(const KParams &P, const void *src, void *dst, const
                              char *Mnext, hipStream_t st) {
     const int gx = (P.Nr + TWO_TW - 1) / TWO_TW, gy = (P.Nz + TWO_TH - 1) / TWO_TH;
     const Planes A = step_planes(P, store_of<S>(), MODE_AB, src, dst, Mprev, Mnext);
-    k_step_two<S><<<dim3(gx * gy), dim3(TWO_CW * TWO_CH), 0, st>>>(P, A, (const S *)src,
-                                                                   (S *)dst, Mprev, Mnext);
+    k_step_two<S><<<dim3(two_grid_blocks(gx, gy)), dim3(TWO_CW * TWO_CH), 0, st>>>(
+        P, A, (const S *)src, Mprev);
+    return hipGetLastError();
+}
+
+void two_tile_shape(int *tw, int *th) {
+    *tw = TWO_TW;
+    *th = TWO_TH;
+}
+
+hipError_t launch_step_two_batch(int storage, const TwoDesc *D, const int2 *tiles, int t0,
+                                 int ntiles, int phase, hipStream_t st) {
+    const int blocks = ntiles < 8 ? 8 : ntiles;  // every XCD chunk needs a block
+    const dim3 grid(blocks), block(TWO_CW * TWO_CH);
+    if (storage == STORE_F16)
+        k_step_two_batch<__half><<<grid, block, 0, st>>>(D, tiles, t0, ntiles, phase);
+    else if (storage == STORE_BF16)
+        k_step_two_batch<__hip_bfloat16><<<grid, block, 0, st>>>(D, tiles, t0, ntiles, phase);
+    else
+        k_step_two_batch<float><<<grid, block, 0, st>>>(D, tiles, t0, ntiles, phase);
     return hipGetLastError();
 }
 

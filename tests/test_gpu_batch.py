@@ -172,3 +172,64 @@ def test_destroying_a_batched_member_is_refused(gpu):
     for lat in a:
         lat.close()
     assert not a[0].handle
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_two_step_batch_equals_alone(gpu, storage):
+    """A batch of AB2 members (two steps per launch over all members) gives
+    every member the result it gets alone, through graph bundles, plain
+    pairs and odd single steps, members joining with either buffer current;
+    degenerate members included."""
+    say("two-step batch vs alone", storage)
+    from paper_1806_10241_amd import axlb
+    cases = members() + [I.couette_poiseuille_conduction(Nr=65, Nz=1, r_inner=5.0),
+                         I.rotating_lid_cylinder(Nr=3, Nz=2, Re=50.0, Ri=0.5)]
+    alone = [axlb.Lattice(c, storage=storage, layout="ab2") for c in cases]
+    batched = [axlb.Lattice(c, storage=storage, layout="ab2") for c in cases]
+    alone[1].step(1)
+    batched[1].step(1)
+    b = axlb.Batch(batched)
+    for n in (101, 100, 3, 2, 1):
+        b.step(n)
+    b.sync()
+    for lat in alone:
+        lat.step(207)
+    for la, lb in zip(alone, batched):
+        assert lb.steps == la.steps
+        assert la.save() == lb.save()
+    with pytest.raises(axlb.AxlbError):
+        b.set_schedule(0, 0)
+    b.close()
+
+
+def test_two_step_batched_workload_members_match_oracle(gpu, orc):
+    """The 256-instance batched workload as AB2 members, 1000 steps: 8
+    sampled members against the FP64 oracle at the FP32 parity bars."""
+    from test_gpu_parity import TOL, TOL_DRHO, assert_parity, field_errors
+    say("two-step batched workload vs oracle")
+    from paper_1806_10241_amd import axlb
+    cases = I.batched_annuli(256, seed=4)
+    lats = [axlb.Lattice(c, layout="ab2") for c in cases]
+    b = axlb.Batch(lats)
+    b.step(1000)
+    b.sync()
+    sample = sorted(range(len(cases)), key=lambda k: cases[k]["Nr"] * cases[k]["Nz"])[:8]
+    for k in sample:
+        c = cases[k]
+        ref = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
+        ref.step(1000)
+        got, want = lats[k].fields(), ref.fields()
+        say("  member %d (%d x %d): %s" % (k, c["Nr"], c["Nz"], {
+            f: "%.2e" % e for f, (e, _) in field_errors(got, want).items()}))
+        assert_parity(got, want, TOL["f32"], "member %d" % k, TOL_DRHO["f32"])
+    b.close()
+
+
+def test_batch_members_share_one_layout(gpu):
+    from paper_1806_10241_amd import axlb
+    cases = members()[:2]
+    lats = [axlb.Lattice(cases[0], layout="aa"), axlb.Lattice(cases[1], layout="ab2")]
+    with pytest.raises(axlb.AxlbError):
+        axlb.Batch(lats)
+    with pytest.raises(axlb.AxlbError):
+        axlb.Batch([axlb.Lattice(cases[0], layout="ab")])
