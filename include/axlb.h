@@ -57,16 +57,16 @@ extern "C" {
 #define AXLB_LAYOUT_AB 1 /* two population buffers, pull streaming              */
 #define AXLB_LAYOUT_AB2 2 /* two buffers, two time steps per launch (below)     */
 /* AXLB_LAYOUT_AB2 holds the same two buffers as AB.  One launch advances two
- * time steps: a workgroup takes a 30 x 14 tile and the one-node ring around
+ * time steps: a workgroup takes a 30 x 22 tile and the one-node ring around
  * it through the first step, keeping the populations and lagged fields in
  * LDS, then takes its tile through the second step.  The results are
  * bit-identical to AB; each pair of steps reads and writes the state once.
  * An odd step count ends with one AB step.  Choosing a layout: AB2 moves
  * half the bytes per step and wins wherever the step is bound by memory
- * (measured with FP32 storage: 1024 x 2048 AB2 38k against AA 35k MLUPS,
- * 2048 x 4096 AB2 42k against AA 25k); with 16-bit storage, where the step
- * is bound by latency and arithmetic, AA is faster at 1024 x 2048 (52k
- * against 42k).  AA needs one population buffer instead of two. */
+ * (measured with FP32 storage: 1024 x 2048 AB2 41k against AA 35k MLUPS,
+ * 2048 x 4096 AB2 40k against AA 25k); with 16-bit storage, where the step
+ * is bound by arithmetic, AA is faster at 1024 x 2048 (53k against 48k).
+ * AA needs one population buffer instead of two. */
 
 /* ---- time level of the central differences in the geometric sources ----
  * (eq. 4b, 4c, 7, 9; Section 3.2 only says "central difference").
@@ -276,7 +276,7 @@ int axlb_load(axlb_lattice *lat, const void *host, size_t bytes);
  * it); axlb_autotune times every shape for steps_per_trial steps on the
  * lattice itself, restores the state it found, selects the fastest, and
  * returns the per-step times in ms_per_step[AXLB_NTILES] (may be NULL).
- * The two-step launches of AXLB_LAYOUT_AB2 use a fixed 30 x 14 tile; the
+ * The two-step launches of AXLB_LAYOUT_AB2 use a fixed 30 x 22 tile; the
  * selected shape applies to its single steps. */
 #define AXLB_NTILES 8
 int axlb_tile_shape(int tile, int *tile_r, int *tile_z);

@@ -175,7 +175,7 @@ static void drop_batch_graphs(axlb_batch *b) {
 // rows, and small members are mostly rim.
 static int build_worklist_two(axlb_batch *b) {
     int tw, th;
-    two_tile_shape(&tw, &th);
+    two_batch_tile_shape(&tw, &th);
     std::vector<TwoDesc> desc(b->members.size());
     std::vector<int2> tiles;
     for (size_t m = 0; m < b->members.size(); ++m) {

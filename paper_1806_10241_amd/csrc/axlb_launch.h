@@ -55,8 +55,8 @@ struct TwoDesc {
     int cur0;              // the member's pair at batch creation
     int gx;                // tiles along r
 };
-// Interior tile of the two-step kernel (nodes along r, along z).
-void two_tile_shape(int *tw, int *th);
+// Interior tile of the batched two-step kernel (nodes along r, along z).
+void two_batch_tile_shape(int *tw, int *th);
 // Work-list entries (member, tile index within the member).
 hipError_t launch_step_two_batch(int storage, const TwoDesc *D, const int2 *tiles, int t0,
                                  int ntiles, int phase, hipStream_t st);

@@ -21,10 +21,18 @@
 namespace axlb {
 
 // Cell block of a workgroup: one thread per cell; a wavefront holds two rows
-// of 32 cells.  Every thread computes one cell of step t; the 30 x 14 tile
-// of step t + 1 is 82% of them.
-constexpr int TWO_CW = 32, TWO_CH = 16;
+// of 32 cells.  Every thread computes one cell of step t; the 30 x 22 tile
+// of step t + 1 is 86% of them.  The block's LDS (19 population planes and
+// 4 lagged-field planes, 70.7 KB in FP32) lets two workgroups, 24
+// wavefronts, share a compute unit, as three 32 x 16 blocks did; the
+// taller block recomputes less of its ring (1024 x 2048 FP32: 101.8 us
+// per two steps against 104.8 us for 32 x 16).
+constexpr int TWO_CW = 32, TWO_CH = 24;
 constexpr int TWO_TW = TWO_CW - 2, TWO_TH = TWO_CH - 2;
+// The batch kernel keeps 32 x 16 blocks (three per compute unit): its
+// members are 48 to 512 nodes tall, and a taller block wastes more of its
+// rows on them (256 uneven annuli: 24.7k MLUPS against 24.3k).
+constexpr int BATCH_CH = 16, BATCH_TH = BATCH_CH - 2;
 
 // The LDS block of post-collision populations as a population source for
 // pull_all: node (i, j) sits in cell (i - i0 + 1, j - j0 + 1).
@@ -76,12 +84,12 @@ __device__ __forceinline__ void pull_lds_all(const S (&A)[NPOP][H][W], int a, in
 // Mprev also serve the general path of the lattice's edge cells.  Every
 // thread reaches the barrier and the end (no early return), so a workgroup
 // may call it for one tile after another.
-template <class S>
+template <class S, int H>
 __device__ __forceinline__ void step_two_tile(const KParams &P, const Planes &A, const S *src,
                                               const char *__restrict__ Mprev, int i0, int j0,
-                                              S (&pop)[NPOP][TWO_CH][TWO_CW],
-                                              float (&lag)[NLAG][TWO_CH][TWO_CW]) {
-    constexpr int W = TWO_CW, H = TWO_CH;
+                                              S (&pop)[NPOP][H][TWO_CW],
+                                              float (&lag)[NLAG][H][TWO_CW]) {
+    constexpr int W = TWO_CW, TH = H - 2;
     const int a = (int)threadIdx.x / W, b = (int)threadIdx.x % W;
 
     // step t for this thread's cell
@@ -123,7 +131,7 @@ __device__ __forceinline__ void step_two_tile(const KParams &P, const Planes &A,
 
     // step t + 1 for the tile's own nodes, from LDS
     const int i = i0 - 1 + a, j = j0 - 1 + b;
-    if (a >= 1 && a <= TWO_TH && b >= 1 && b <= TWO_TW && i < P.Nz && j < P.Nr) {
+    if (a >= 1 && a <= TH && b >= 1 && b <= TWO_TW && i < P.Nz && j < P.Nr) {
         float f[9], g[5], h[5], d[5];
         if (interior_node(P, i, j)) {
             pull_lds_all<S>(pop, a, b, f, g, h);
@@ -205,7 +213,7 @@ __global__ void __launch_bounds__(TWO_CW *TWO_CH) k_step_two(const KParams P, co
     const int gx = (P.Nr + TWO_TW - 1) / TWO_TW, gy = (P.Nz + TWO_TH - 1) / TWO_TH;
     int tx, ty;
     if (!two_tile_of(gx, gy, (int)blockIdx.x, tx, ty)) return;  // padding: the whole workgroup
-    step_two_tile<S>(P, A, src, Mprev, ty * TWO_TH, tx * TWO_TW, pop, lag);
+    step_two_tile<S, TWO_CH>(P, A, src, Mprev, ty * TWO_TH, tx * TWO_TW, pop, lag);
 }
 
 // Two steps of many lattices (a batch of two-buffer members): one
@@ -218,11 +226,11 @@ __global__ void __launch_bounds__(TWO_CW *TWO_CH) k_step_two(const KParams P, co
 // most 80 VGPRs; left alone the compiler takes 84 for the parameters it
 // reads from the descriptors.
 template <class S>
-__global__ void __launch_bounds__(TWO_CW *TWO_CH, 6) k_step_two_batch(const TwoDesc *__restrict__ D,
+__global__ void __launch_bounds__(TWO_CW *BATCH_CH, 6) k_step_two_batch(const TwoDesc *__restrict__ D,
                                                                     const int2 *__restrict__ tile_inst,
                                                                     int t0, int ntiles, int phase) {
-    __shared__ S pop[NPOP][TWO_CH][TWO_CW];
-    __shared__ float lag[NLAG][TWO_CH][TWO_CW];
+    __shared__ S pop[NPOP][BATCH_CH][TWO_CW];
+    __shared__ float lag[NLAG][BATCH_CH][TWO_CW];
     const int G = gridDim.x, bk = blockIdx.x;
     const int xcd = bk & 7, k = bk >> 3;
     // chunk sizes follow the block counts per XCD, so that with one block
@@ -236,8 +244,8 @@ __global__ void __launch_bounds__(TWO_CW *TWO_CH, 6) k_step_two_batch(const TwoD
         const TwoDesc *d = D + e.x;
         const int c = d->cur0 ^ phase;
         const int local = e.y;
-        step_two_tile<S>(d->P, d->pl[c], static_cast<const S *>(d->src[c]), d->lag[c],
-                         (local / d->gx) * TWO_TH, (local % d->gx) * TWO_TW, pop, lag);
+        step_two_tile<S, BATCH_CH>(d->P, d->pl[c], static_cast<const S *>(d->src[c]), d->lag[c],
+                                   (local / d->gx) * BATCH_TH, (local % d->gx) * TWO_TW, pop, lag);
         __syncthreads();  // the LDS block is refilled by the next entry
     }
 }
@@ -252,15 +260,15 @@ static hipError_t step_two_t(const KParams &P, const void *src, void *dst, const
     return hipGetLastError();
 }
 
-void two_tile_shape(int *tw, int *th) {
+void two_batch_tile_shape(int *tw, int *th) {
     *tw = TWO_TW;
-    *th = TWO_TH;
+    *th = BATCH_TH;
 }
 
 hipError_t launch_step_two_batch(int storage, const TwoDesc *D, const int2 *tiles, int t0,
                                  int ntiles, int phase, hipStream_t st) {
     const int blocks = ntiles < 8 ? 8 : ntiles;  // every XCD chunk needs a block
-    const dim3 grid(blocks), block(TWO_CW * TWO_CH);
+    const dim3 grid(blocks), block(TWO_CW * BATCH_CH);
     if (storage == STORE_F16)
         k_step_two_batch<__half><<<grid, block, 0, st>>>(D, tiles, t0, ntiles, phase);
     else if (storage == STORE_BF16)
