@@ -267,8 +267,13 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, 
     arrival, done, steps_of = {}, {}, {}
     pending = list(trace)
     t0 = time.perf_counter()
+    reported = 0.0
     while pending or len(done) < len(arrival):
         now = time.perf_counter() - t0
+        if now - reported >= 30.0:  # progress of a long trace
+            reported = now
+            print("bench: served %d of %d requests (%d arrived) after %.0f s"
+                  % (len(done), n, len(arrival), now), file=sys.stderr, flush=True)
         while pending and pending[0][0] <= now:
             at, case, st = pending.pop(0)
             rid = pool.submit(case, st, tol=tol, max_steps=max_steps)
