@@ -254,6 +254,12 @@ static int ensure_graph(axlb_lattice *L, long len, int k) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess)
         return fail(L, AXLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    // upload it now, so that its first replay costs no more than the others
+    e = hipGraphUpload(x, L->stream);
+    if (e != hipSuccess) {
+        (void)hipGraphExecDestroy(x);
+        return fail(L, AXLB_EDEVICE, std::string("graph upload: ") + hipGetErrorString(e));
+    }
     L->graphs[key] = x;
     return AXLB_OK;
 }
