@@ -178,6 +178,8 @@ static int build_worklist_two(axlb_batch *b) {
     two_batch_tile_shape(&tw, &th);
     std::vector<TwoDesc> desc(b->members.size());
     std::vector<int2> tiles;
+    b->group.clear();
+    size_t group_bytes = 0;
     for (size_t m = 0; m < b->members.size(); ++m) {
         axlb_lattice *L = b->members[m];
         TwoDesc &d = desc[m];
@@ -192,10 +194,19 @@ static int build_worklist_two(axlb_batch *b) {
         d.cur0 = L->cur ^ b->phase;
         d.gx = (L->Nr + tw - 1) / tw;
         const int gy = (L->Nz + th - 1) / th;
+        const int first = (int)tiles.size();
         for (int t = 0; t < d.gx * gy; ++t) tiles.push_back(make_int2((int)m, t));
+        // groups of consecutive members whose states (both buffers) fit
+        // GROUP_BYTES, as for AA members
+        const size_t bytes = 2 * L->lay.pop_bytes + 2 * L->lay.lag_bytes;
+        if (m == 0 || group_bytes + bytes > GROUP_BYTES) {
+            b->group.push_back(first);
+            group_bytes = 0;
+        }
+        group_bytes += bytes;
     }
     const int n = (int)tiles.size();
-    b->group.assign({0, n});
+    b->group.push_back(n);
     if (b->d_two) (void)hipFree(b->d_two);
     if (b->d_two_tiles) (void)hipFree(b->d_two_tiles);
     b->d_two = nullptr;
@@ -282,13 +293,15 @@ static void advance_members(axlb_batch *b, long n) {
     for (axlb_lattice *L : b->members) L->steps += n;
 }
 
-// One two-step launch of every member of a two-buffer batch.
-static int two_launch(axlb_batch *b, int phase) {
-    const hipError_t e = launch_step_two_batch(b->storage, b->d_two, b->d_two_tiles, 0,
-                                               b->ntiles, phase, b->stream);
+// One two-step launch of the work-list entries [t0, t1) of a two-buffer
+// batch (every member by default).
+static int two_launch(axlb_batch *b, int phase, int t0, int t1, hipStream_t st) {
+    const hipError_t e = launch_step_two_batch(b->storage, b->d_two, b->d_two_tiles, t0, t1 - t0,
+                                               phase, st);
     if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
     return AXLB_OK;
 }
+static int two_launch(axlb_batch *b, int phase) { return two_launch(b, phase, 0, b->ntiles, b->stream); }
 
 // After `launches` two-step launches: two steps each, one buffer flip each.
 static void advance_two(axlb_batch *b, long launches) {
@@ -309,9 +322,20 @@ static int batch_step_two(axlb_batch *b, long n) {
             const int k = b->phase;
             if (!b->graph[k]) {
                 BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                // group by group, alternating between two chains, as for AA
+                // members: a group's two buffers stay in the Infinity Cache
+                // through its 50 launches
                 int rc = AXLB_OK;
-                for (long s = 0; s < BUNDLE / 2 && rc == AXLB_OK; ++s)
-                    rc = two_launch(b, (int)((k + s) & 1));
+                hipError_t fe = hipEventRecord(b->fork, b->stream);
+                if (fe == hipSuccess) fe = hipStreamWaitEvent(b->side, b->fork, 0);
+                if (fe != hipSuccess) rc = bfail(b, AXLB_EDEVICE, "batch graph fork failed");
+                for (size_t gi = 0; gi + 1 < b->group.size() && rc == AXLB_OK; ++gi)
+                    for (long s = 0; s < BUNDLE / 2 && rc == AXLB_OK; ++s)
+                        rc = two_launch(b, (int)((k + s) & 1), b->group[gi], b->group[gi + 1],
+                                        gi % 2 ? b->side : b->stream);
+                fe = hipEventRecord(b->join, b->side);
+                if (fe == hipSuccess) fe = hipStreamWaitEvent(b->stream, b->join, 0);
+                if (fe != hipSuccess && rc == AXLB_OK) rc = bfail(b, AXLB_EDEVICE, "batch graph join failed");
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(b->stream, &g);
                 if (rc != AXLB_OK) {
