@@ -176,3 +176,23 @@ def test_table4_czochralski_stream_function(orc):
     assert abs(hi / scale - TABLE4[100.0]) <= 1.5e-2 * TABLE4[100.0], hi / scale
     i, j = np.unravel_index(np.argmin(psi), psi.shape)
     assert lo < 0 and (i + 0.5) / N > 0.6 and (j + 1) / N <= c["R_x"] / N + 0.05
+
+
+def test_stream_function_of_hagen_poiseuille_flow(orc):
+    """d psi/d y = -y u_x with psi = 0 on the axis: for the pipe flow
+    u_z = g (R^2 - r^2) / (4 nu), psi = -(g / 4 nu)(R^2 r^2 / 2 - r^4 / 4),
+    whose wall value -g R^4 / (16 nu) is the axial flux over 2 pi; the
+    oracle's psi (at the cell edges r = j + 1) against it, and uniform
+    along the periodic axis."""
+    from test_oracle_lattice import pipe_case
+    c = pipe_case(Omega=0.0)
+    L = orc.Lattice(c, deriv_mode=2, fields={"T": np.full((c["Nz"], c["Nr"]), 0.5)})
+    L.step(12000)
+    psi, lo, hi = L.stream_function()
+    R, g, nu = float(c["Nr"]), c["g_axial"], c["nu"]
+    r = np.arange(c["Nr"]) + 1.0
+    want = -(g / (4 * nu)) * (R * R * r * r / 2 - r ** 4 / 4)
+    assert rel_l2(psi[0], want) < 5e-3
+    assert abs(psi[0][-1] / (-g * R ** 4 / (16 * nu)) - 1) < 5e-3
+    assert np.abs(psi - psi[0]).max() < 1e-12 * np.abs(want).max()
+    assert lo == pytest.approx(psi.min()) and hi == pytest.approx(max(psi.max(), 0.0))
