@@ -368,11 +368,14 @@ def headline(args, case, stream):
     if args.tile >= 0:
         lat.set_tile(args.tile)
         tune = None
+    elif args.layout == "ab2":
+        tune = None  # the two-step launches have one tile; the single-step one is unused
     else:
         best, ms = lat.autotune(steps_per_trial=40)
         tune = {"%dx%d" % axlb.tile_shape(t): round(m * 1e3, 2) for t, m in enumerate(ms)}
         print("bench: autotune us/step per tile %s" % tune, file=sys.stderr, flush=True)
     _, tile_rz = lat.tile()
+    tile = "%dx%d" % tile_rz if args.layout != "ab2" else "30x22 (two-step launch)"
     if args.single_launches:
         lat.set_graphs(False)
     lat.step(args.warmup)
@@ -406,7 +409,7 @@ def headline(args, case, stream):
     print("bench: timed %d steps in %.3f s (events %.4f ms/step)" % (args.steps, wall, ms_per_step),
           file=sys.stderr, flush=True)
     return {"ms_per_step": ms_per_step, "mlups": nodes * args.steps / (ms / 1e3) / 1e6,
-            "launch": launch, "tile": "%dx%d" % tile_rz, "autotune_us_per_step": tune,
+            "launch": launch, "tile": tile, "autotune_us_per_step": tune,
             "finite": bool(r == r)}
 
 
