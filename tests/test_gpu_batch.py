@@ -233,3 +233,25 @@ def test_batch_members_share_one_layout(gpu):
         axlb.Batch(lats)
     with pytest.raises(axlb.AxlbError):
         axlb.Batch([axlb.Lattice(cases[0], layout="ab")])
+
+
+def test_two_step_batch_groups_on_two_streams_equal_alone(gpu):
+    """AB2 members whose states exceed one cache group: the bundle's 50
+    two-step launches run group by group on two streams; every member
+    still ends bit-identical to stepping alone (two bundles and a partial
+    one)."""
+    say("two-step batch groups on two streams")
+    from paper_1806_10241_amd import axlb
+    cases = [I.annulus_convection(Nr=640, Nz=512, Ra=10 ** (3 + 0.4 * k), seed=90 + k)
+             for k in range(5)]
+    assert sum(axlb.state_bytes(c["Nr"], c["Nz"], layout="ab2") for c in cases) > 2 * (80 << 20)
+    alone = [axlb.Lattice(c, layout="ab2") for c in cases]
+    batched = [axlb.Lattice(c, layout="ab2") for c in cases]
+    b = axlb.Batch(batched)
+    b.step(237)
+    b.sync()
+    for lat in alone:
+        lat.step(237)
+    for la, lb in zip(alone, batched):
+        assert la.save() == lb.save()
+    b.close()

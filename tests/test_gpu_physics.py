@@ -130,6 +130,28 @@ def test_table4_czochralski_stream_function(gpu, Re_x, bar):
     assert (rc < 0.35) if Re_x == 100.0 else (0.4 <= rc < 0.5)
 
 
+@pytest.mark.parametrize("Ra", [1e3, 1e4, 1e5])
+def test_annulus_workload_steady_nusselt(gpu, Ra):
+    """The annulus workload (configuration 2: 256 x 256, H/L = 1, R_o/R_i = 2,
+    Pr = 0.71) run to residual 1e-8: the inner and outer wall Nusselt numbers
+    balance at steady state, and halving the grid (128 x 128) moves the mean
+    by less than 1%.  (Table 1 is for H/L = 2 and is pinned elsewhere.)"""
+    say("annulus workload, Ra", Ra)
+    from paper_1806_10241_amd import axlb
+    means = {}
+    for N in (128, 256):
+        c = I.annulus_convection(Nr=N, Nz=N, Pr=0.71, Ra=Ra)
+        lat = axlb.Lattice(c, layout="ab2")
+        r = run_to_steady(lat, tol=1e-8, chunk=10000, max_steps=8_000_000)
+        nu_i, nu_o, mean = lat.nusselt()
+        say("  %d x %d: steps %d residual %.2e Nu_i %.4f Nu_o %.4f mean %.4f"
+            % (N, N, lat.steps, r, nu_i, nu_o, mean))
+        assert r < 1e-8
+        assert abs(nu_i - nu_o) < 1e-2 * mean
+        means[N] = mean
+    assert abs(means[128] - means[256]) < 1e-2 * means[256]
+
+
 def test_steady_nusselt_matches_oracle(gpu, orc):
     say("steady Nu vs oracle")
     from paper_1806_10241_amd import axlb
