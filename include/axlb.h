@@ -64,7 +64,7 @@ extern "C" {
  * An odd step count ends with one AB step.  Choosing a layout: AB2 moves
  * half the bytes per step and wins wherever the step is bound by memory
  * (measured with FP32 storage: 1024 x 2048 AB2 41k against AA 35k MLUPS,
- * 2048 x 4096 AB2 40k against AA 25k); with 16-bit storage, where the step
+ * 2048 x 4096 AB2 42k against AA 25k); with 16-bit storage, where the step
  * is bound by arithmetic, AA is faster at 1024 x 2048 (53k against 48k).
  * AA needs one population buffer instead of two. */
 
