@@ -148,6 +148,11 @@ typedef struct {
                             allocates (and frees) its own                   */
     size_t device_bytes; /* size of device_buf                              */
     int deriv;           /* AXLB_DERIV_LAGGED (default) | AXLB_DERIV_CURRENT */
+    int row0;            /* global index of row 0 when the lattice is a slab of
+                            a taller one (HALO faces), >= 0, default 0: the
+                            stochastic rounding of 16-bit stores keys on
+                            global rows, so slabs reproduce the uncut lattice
+                            bit for bit in every storage                    */
 } axlb_options;
 
 /* Bytes of device memory a lattice of this size holds (populations, lagged

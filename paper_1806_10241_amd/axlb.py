@@ -69,7 +69,7 @@ class Relax(C.Structure):
 class Options(C.Structure):
     _fields_ = [("storage", C.c_int), ("layout", C.c_int), ("T_ref", C.c_double),
                 ("stream", C.c_void_p), ("device", C.c_int), ("device_buf", C.c_void_p),
-                ("device_bytes", C.c_size_t), ("deriv", C.c_int)]
+                ("device_bytes", C.c_size_t), ("deriv", C.c_int), ("row0", C.c_int)]
 
 
 class Request(C.Structure):
@@ -193,11 +193,13 @@ class Lattice:
     fields; needs layout "ab").
     stream: a ``torch.cuda.Stream`` to run on (None: the library's own).
     torch_memory: lend the state as a torch CUDA tensor (else hipMalloc).
+    row0: global index of row 0 for a slab of a taller lattice (the
+    rounding keys of 16-bit storage).
     """
 
     def __init__(self, case: dict, storage: str = "f32", layout: str = "aa", stream=None,
                  device: int = 0, torch_memory: bool = True, init_fields: bool = True,
-                 deriv: str = "lagged"):
+                 deriv: str = "lagged", row0: int = 0):
         lib = load()
         self._lib = lib
         self._h = _vp()
@@ -210,6 +212,7 @@ class Lattice:
         opt.storage = STORAGE[storage]
         opt.layout = LAYOUT[layout]
         opt.deriv = DERIV[deriv]
+        opt.row0 = int(row0)
         opt.T_ref = float(case.get("T_ref", 0.5))
         opt.device = int(device)
         self._stream = stream

@@ -103,6 +103,7 @@ KParams axlb::make_params(const axlb_lattice *L) {
         P.halo_pop[f] = L->halo[f];
         P.halo_lag[f] = L->halo[f] + L->lay.halo_pop_bytes;
     }
+    P.row0 = L->row0;
     P.okinds = 0;
     for (int f = 0; f < 2; ++f) {
         P.split[f] = L->split[f];
@@ -351,6 +352,8 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
         return fail(nullptr, AXLB_EINVAL,
                     "current-step derivatives need the two-buffer, one-step layout");
     if (!std::isfinite(O.T_ref)) return fail(nullptr, AXLB_EINVAL, "T_ref must be finite");
+    if (O.row0 < 0 || (long long)O.row0 + Nz > INT32_MAX)
+        return fail(nullptr, AXLB_EINVAL, "row0 must be >= 0 and row0 + Nz below 2^31");
 
     axlb_lattice *L = new (std::nothrow) axlb_lattice();
     if (!L) return fail(nullptr, AXLB_ENOMEM, "host allocation failed");
@@ -368,6 +371,7 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     L->storage = O.storage;
     L->layout = O.layout;
     L->deriv = O.deriv;
+    L->row0 = O.row0;
     L->T_ref = O.T_ref;
     for (int f = 0; f < 4; ++f) {
         L->kind[f][0] = AXLB_NOSLIP;
@@ -540,8 +544,9 @@ int axlb_set_fields(axlb_lattice *L, const double *rho, const double *ur, const 
     }
     HIP_TRY(L, hipMemcpyAsync(L->fld, h.data(), 5 * N * sizeof(double), hipMemcpyHostToDevice,
                               L->stream));
-    hipError_t e = launch_init(L->P, L->storage, L->layout == AXLB_LAYOUT_AA, L->pop[0], L->fld,
-                               L->lag[0], L->stream);
+    hipError_t e = launch_init(L->P, L->storage, L->layout == AXLB_LAYOUT_AA,
+                               L->deriv == AXLB_DERIV_LAGGED, L->pop[0], L->fld, L->lag[0],
+                               L->stream);
     if (e != hipSuccess) return fail(L, AXLB_EDEVICE, std::string("init launch: ") + hipGetErrorString(e));
     HIP_TRY(L, hipStreamSynchronize(L->stream));
     L->steps = 0;
@@ -750,6 +755,14 @@ struct Header {
     uint64_t pop_bytes, lag_bytes;
 };
 static const uint64_t MAGIC = 0x31424c584131ULL;  // "1AXLB1"
+// An image of offset-encoded bfloat16 populations (every form with lagged
+// derivatives) carries its own magic: such populations mean something only
+// with the lagged fields, so a lattice with current-step derivatives (plain
+// bfloat16) must not load them, nor the other way round.
+static const uint64_t MAGIC_ENC = 0x32424c584131ULL;  // "1AXLB2"
+static uint64_t image_magic(const axlb_lattice *L) {
+    return L->storage == AXLB_BF16 && L->deriv == AXLB_DERIV_LAGGED ? MAGIC_ENC : MAGIC;
+}
 
 int axlb_state_size(const axlb_lattice *L, size_t *bytes) {
     if (!L || !bytes) return fail(nullptr, AXLB_EINVAL, "NULL argument");
@@ -767,7 +780,8 @@ int axlb_save(axlb_lattice *L, void *host, size_t bytes) {
     // the buffers the next step reads: AA's one population buffer and the
     // lagged block of the step parity; the two-buffer layouts' current pair
     const int k = two_buffers(L) ? L->cur : (int)(L->steps & 1);
-    Header h = {MAGIC, L->Nr, L->Nz, L->storage, L->layout, L->steps, L->lay.pop_bytes, L->lay.lag_bytes};
+    Header h = {image_magic(L), L->Nr, L->Nz, L->storage, L->layout, L->steps, L->lay.pop_bytes,
+                L->lay.lag_bytes};
     char *p = (char *)host;
     std::memcpy(p, &h, sizeof(h));
     void *pop = two_buffers(L) ? L->pop[k] : L->pop[0];
@@ -786,7 +800,7 @@ int axlb_load(axlb_lattice *L, const void *host, size_t bytes) {
     Header h;
     if (bytes < need) return fail(L, AXLB_EINVAL, "image too small");
     std::memcpy(&h, host, sizeof(h));
-    if (h.magic != MAGIC || h.Nr != L->Nr || h.Nz != L->Nz || h.storage != L->storage ||
+    if (h.magic != image_magic(L) || h.Nr != L->Nr || h.Nz != L->Nz || h.storage != L->storage ||
         h.layout != L->layout || h.pop_bytes != L->lay.pop_bytes || h.lag_bytes != L->lay.lag_bytes ||
         h.steps < 0)
         return fail(L, AXLB_EINVAL, "image does not match this lattice");

@@ -7,7 +7,8 @@
 // its tile plus a one-node ring around it, keeps the four output fields of
 // all of them in LDS, and then differences from LDS.  The ring nodes are
 // streamed again by their own workgroups (reads that mostly hit L2); no
-// lagged-field buffer is read or written.
+// lagged-field buffer is read or written, and so the populations are stored
+// without the offset encoding of bfloat16 (which takes the lagged fields).
 #include "axlb_device.h"
 #include "axlb_launch.h"
 #include "axlb_node.h"
@@ -24,7 +25,7 @@ __device__ __forceinline__ void pull_node(const KParams &P, const Planes &A, con
         gather_planes<S>(A, ((unsigned)i * (unsigned)P.pitch + (unsigned)j) * (unsigned)sizeof(S),
                          f, g, h);
     else
-        gather<S, MODE_AB>(P, src, i, j, false, f, g, h);
+        gather<S, MODE_AB, false>(P, src, nullptr, i, j, false, f, g, h);
 }
 
 // Output fields of a node into the LDS tile F[4][H][W] at (a, b).
@@ -101,11 +102,11 @@ __global__ void __launch_bounds__(BX * BY) k_current(const KParams P, const Plan
         collide_adv(g, Hs.ux, Hs.uy, Hs.psi, Hs.psi, Hs.hSpsi, P.og12, P.og3, P.og4);
         collide_adv(h, Hs.ux, Hs.uy, P.Tref + Hs.dphi, Hs.dphi, Hs.hSphi, P.oh12, P.oh3, P.oh4);
         if (interior)
-            scatter_planes<S>(A, local_offset(((unsigned)i * (unsigned)P.pitch + (unsigned)j) *
-                                              (unsigned)sizeof(S)),
-                              i, j, f, g, h);
+            scatter_planes<S, false>(
+                A, local_offset(((unsigned)i * (unsigned)P.pitch + (unsigned)j) * (unsigned)sizeof(S)),
+                i + P.row0, j, f, g, h, Lag4{});
         else
-            scatter<S, MODE_AB>(P, dst, i, j, false, f, g, h);
+            scatter<S, MODE_AB, false>(P, dst, i, j, false, f, g, h, Lag4{});
     } else {
         const long long N = (long long)P.Nr * P.Nz, k = (long long)i * P.Nr + j;
         out[k] = 1.0 + (double)Hs.drho;

@@ -113,6 +113,9 @@ struct KParams {
     // planes (lag_ld layout)
     const void *halo_pop[2];
     const char *halo_lag[2];
+    // Global index of row 0 (a slab of a taller lattice): the stochastic
+    // rounding of 16-bit stores keys on global rows.
+    int row0;
 };
 
 // Plane addresses of one step launch, for the tile workgroups of the step

@@ -34,6 +34,7 @@ struct axlb_lattice {
     double T_ref = 0.5;
     axlb_relax relax{};
     int storage = 0, layout = 0, deriv = 0;
+    int row0 = 0;  // global index of row 0 (slabs)
     int cur = 0;  // two-buffer layouts: the population and lagged-field pair the next step reads
     int kind[4][3]{};
     double val[4][3]{};

@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(TX * TY) k_fields(const KParams P, const S *sr
     if (i >= P.Nz || j >= P.Nr) return;
     const bool interior = interior_node(P, i, j);
     float f[9], g[5], h[5];
-    gather<S, MODE>(P, src, i, j, interior, f, g, h);
+    gather<S, MODE>(P, src, Mprev, i, j, interior, f, g, h);
     const Moments m = moments(f, g, h);
     float d[5];
     derivatives<S>(P, Mprev, i, j, interior, d);
@@ -101,13 +101,14 @@ __global__ void __launch_bounds__(TX * TY) k_fields(const KParams P, const S *sr
 // per axis for D2Q9; the D2Q5 weights of s (cs2 + u_a^2 +- u_a)/2 and the
 // remainder at rest), computed in FP64 and stored shifted.  AA stores them
 // as the even phase would (post-collision in plane opp q), AB in plane q.
-// The lagged fields start as the given fields.
+// The lagged fields start as the given fields; ENC stores the populations
+// offset-encoded with them (bfloat16 with lagged derivatives).
 __device__ __forceinline__ double w1(int e, double u) {
     const double c = 1.0 / 3.0 + u * u;
     return e == 0 ? 1.0 - c : 0.5 * (c + e * u);
 }
 
-template <class S, bool AA>
+template <class S, bool AA, bool ENC>
 __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
                                                    const double *__restrict__ in, char *M) {
     int i, j;
@@ -118,6 +119,7 @@ __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
     const double rho = in[k], ur = in[N + k], uz = in[2 * N + k], uth = in[3 * N + k];
     const double T = in[4 * N + k];
     const double Tref = (double)P.Tref;
+    const Lag4 L0 = lag_stored<S>((float)uz, (float)ur, (float)uth, (float)(T - Tref));
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int ex = Lat<FLOW>::ex(q), ey = Lat<FLOW>::ey(q);
@@ -125,7 +127,9 @@ __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
         const double w = w1(ex, 0.0) * w1(ey, 0.0);
         const int slot = AA ? Lat<FLOW>::opp(q) : q;
         const float x = (float)(feq - w);
-        Conv<S>::st(A + slot * P.plane + n, x, sr_single(x, skey(i, j, q)));
+        float e = x;
+        if (ENC) e = x - pop_off<FLOW>(q, L0);
+        Conv<S>::st(A + slot * P.plane + n, e, sr_single(x, skey(i + P.row0, j, q)));
     }
     const double psi = rho * uth;
     double ge[5], he[5];
@@ -144,8 +148,14 @@ __global__ void __launch_bounds__(TX * TY) k_init(const KParams P, S *A,
         const double w = q == 0 ? 1.0 / 3.0 : 1.0 / 6.0;
         const int slot = AA ? Lat<SWIRL>::opp(q) : q;
         const float xg = (float)ge[q], xh = (float)(he[q] - w * Tref);
-        Conv<S>::st(A + (GOFF + slot) * P.plane + n, xg, sr_single(xg, skey(i, j, GOFF + q)));
-        Conv<S>::st(A + (HOFF + slot) * P.plane + n, xh, sr_single(xh, skey(i, j, HOFF + q)));
+        float eg = xg, eh = xh;
+        if (ENC) {
+            eg = xg - pop_off<SWIRL>(q, L0);
+            eh = xh - pop_off<THERMAL>(q, L0);
+        }
+        const int gi = i + P.row0;
+        Conv<S>::st(A + (GOFF + slot) * P.plane + n, eg, sr_single(xg, skey(gi, j, GOFF + q)));
+        Conv<S>::st(A + (HOFF + slot) * P.plane + n, eh, sr_single(xh, skey(gi, j, HOFF + q)));
     }
     lag_st<S>(M, 0, P.plane, n, (float)uz);
     lag_st<S>(M, 1, P.plane, n, (float)ur);
@@ -356,11 +366,12 @@ static hipError_t launch_fields_t(const KParams &P, int mode, const void *src, c
 }
 
 template <class S>
-static hipError_t launch_init_t(const KParams &P, bool aa, void *pop, const double *in, char *M,
-                                hipStream_t st) {
+static hipError_t launch_init_t(const KParams &P, bool aa, bool enc, void *pop, const double *in,
+                                char *M, hipStream_t st) {
     const dim3 grid = step_grid(P), block(TX * TY);
-    if (aa) k_init<S, true><<<grid, block, 0, st>>>(P, (S *)pop, in, M);
-    else k_init<S, false><<<grid, block, 0, st>>>(P, (S *)pop, in, M);
+    if (aa) k_init<S, true, kEnc<S>><<<grid, block, 0, st>>>(P, (S *)pop, in, M);
+    else if (enc) k_init<S, false, kEnc<S>><<<grid, block, 0, st>>>(P, (S *)pop, in, M);
+    else k_init<S, false, false><<<grid, block, 0, st>>>(P, (S *)pop, in, M);
     return hipGetLastError();
 }
 
@@ -392,11 +403,11 @@ hipError_t launch_fields(const KParams &P, int storage, int mode, const void *sr
     return launch_fields_t<float>(P, mode, src, Mprev, out, st);
 }
 
-hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
-                       char *M, hipStream_t st) {
-    if (storage == STORE_F16) return launch_init_t<__half>(P, aa, pop, in, M, st);
-    if (storage == STORE_BF16) return launch_init_t<__hip_bfloat16>(P, aa, pop, in, M, st);
-    return launch_init_t<float>(P, aa, pop, in, M, st);
+hipError_t launch_init(const KParams &P, int storage, bool aa, bool enc, void *pop,
+                       const double *in, char *M, hipStream_t st) {
+    if (storage == STORE_F16) return launch_init_t<__half>(P, aa, enc, pop, in, M, st);
+    if (storage == STORE_BF16) return launch_init_t<__hip_bfloat16>(P, aa, enc, pop, in, M, st);
+    return launch_init_t<float>(P, aa, enc, pop, in, M, st);
 }
 
 hipError_t launch_residual(const double *fld, const double *snap, long long N, double *part,

@@ -60,8 +60,10 @@ void two_batch_tile_shape(int *tw, int *th);
 // Work-list entries (member, tile index within the member).
 hipError_t launch_step_two_batch(int storage, const TwoDesc *D, const int2 *tiles, int t0,
                                  int ntiles, int phase, hipStream_t st);
-hipError_t launch_init(const KParams &P, int storage, bool aa, void *pop, const double *in,
-                       char *M, hipStream_t st);
+// enc: offset-encode bfloat16 populations with the lagged fields (every
+// form but the current-step derivatives).
+hipError_t launch_init(const KParams &P, int storage, bool aa, bool enc, void *pop,
+                       const double *in, char *M, hipStream_t st);
 hipError_t launch_residual(const double *fld, const double *snap, long long N, double *part,
                            int nblocks, double *out9, hipStream_t st);
 hipError_t launch_nusselt(const double *T, int Nr, int Nz, int cylinder, double r0, double Ta,

@@ -42,7 +42,7 @@ struct PulledFields {
         int ni = i + di;
         if ((unsigned)ni >= (unsigned)P.Nz) ni += ni < 0 ? P.Nz : -P.Nz;
         float f[9], g[5], h[5];
-        pull_all<false>(P, GlobalPops<S>{P, src}, ni, j + dj, f, g, h);
+        pull_all<false>(P, GlobalPops<S, false>{P, src, nullptr}, ni, j + dj, f, g, h);
         const Moments m = moments(f, g, h);
         const float ir = rcp(1.f + m.drho);
         return v == 0 ? m.jx * ir : v == 1 ? m.jy * ir : v == 2 ? m.psi * ir : m.dphi;
@@ -56,11 +56,11 @@ template <class S, int MODE, bool CUR>
 __device__ double node_T(const KParams &P, const S *src, const char *Mprev, int i, int j) {
     float f[9], g[5], h[5], d[5];
     if (CUR) {
-        pull_all<false>(P, GlobalPops<S>{P, src}, i, j, f, g, h);
+        pull_all<false>(P, GlobalPops<S, false>{P, src, nullptr}, i, j, f, g, h);
         differences(P, PulledFields<S>{P, src, i, j}, i, j, d);
     } else {
         const bool interior = interior_node(P, i, j);
-        gather<S, MODE>(P, src, i, j, interior, f, g, h);
+        gather<S, MODE>(P, src, Mprev, i, j, interior, f, g, h);
         derivatives<S>(P, Mprev, i, j, interior, d);
     }
     const Moments m = moments(f, g, h);

@@ -122,23 +122,148 @@ __device__ __forceinline__ float wall_value(const KParams &P, int face, int c2, 
 }
 
 // ----------------------------------------------------------------------------
+// Offset encoding of bfloat16 populations.  bfloat16 keeps 8 significant
+// bits, and a shifted population f - w_q is dominated by its part linear in
+// the velocity, 3 w_q e_q . u (g by w_q u_theta, h - w_q T_ref by
+// w_q (T - T_ref)), so the store would round away most of what the
+// collision changes.  A bfloat16 slot therefore holds its population minus
+// that linear equilibrium part evaluated with the lagged fields of the node
+// that wrote it, exactly as stored in the lagged-field block of the step
+// (the writer has them in registers, a reader loads them with its
+// derivative stencils): the stored value is the small non-equilibrium
+// remainder plus the change of u over one link, and the reader adds the same
+// FP32 offset back.  FP32 and binary16 storage, and the current-step
+// derivative form (which keeps no lagged fields), store populations as they
+// are.  Which node wrote a slot, and for which direction:
+//  * two buffers, and the AA odd phase reading what the even phase wrote:
+//    the node that holds the slot, for the direction of the plane (AB) or
+//    the opposite one (AA, whose even phase writes f*_q into plane opp q);
+//  * the AA even phase reading what the odd phase pushed: the source node of
+//    the pull form, for the direction of the plane, where the link stays in
+//    the fluid, is reflected at the axis or the free surface, or wraps
+//    periodically; after a wall the node itself, for the direction that hit
+//    the wall (the odd phase applies the wall rule before it stores).
+template <class S>
+constexpr bool kEnc = std::is_same<S, __hip_bfloat16>::value;
+
+// Lagged fields of a node as the lagged-field block holds them (u_x, u_y,
+// u_theta, T - T_ref).
+struct Lag4 {
+    float ux, uy, ut, dT;
+};
+
+// Offset of population q of distribution FLD for lagged fields L: products
+// with +-1 and one rounding per term, so that every path forms the same bits.
+template <int FLD>
+__device__ __forceinline__ float pop_off(int q, const Lag4 &L) {
+    if (FLD == FLOW) {
+        const int ex = Lat<FLOW>::ex(q), ey = Lat<FLOW>::ey(q);
+        float e = 0.f, w3 = 1.f / 12.f;  // 3 w_q: 1/3 along an axis, 1/12 diagonally
+        if (ex != 0 && ey != 0) {
+            e = (ex > 0 ? L.ux : -L.ux) + (ey > 0 ? L.uy : -L.uy);
+        } else if (ex != 0) {
+            e = ex > 0 ? L.ux : -L.ux;
+            w3 = 1.f / 3.f;
+        } else if (ey != 0) {
+            e = ey > 0 ? L.uy : -L.uy;
+            w3 = 1.f / 3.f;
+        }
+        return w3 * e;
+    }
+    const float w = q == 0 ? 1.f / 3.f : 1.f / 6.f;
+    return w * (FLD == SWIRL ? L.ut : L.dT);
+}
+// Offset of plane p (0..18) holding direction p (OPP: the opposite one).
+template <bool OPP>
+__device__ __forceinline__ float plane_off(int p, const Lag4 &L) {
+    if (p < GOFF) return pop_off<FLOW>(OPP ? Lat<FLOW>::opp(p) : p, L);
+    if (p < HOFF) return pop_off<SWIRL>(OPP ? Lat<SWIRL>::opp(p - GOFF) : p - GOFF, L);
+    return pop_off<THERMAL>(OPP ? Lat<THERMAL>::opp(p - HOFF) : p - HOFF, L);
+}
+
+// The lagged fields at node (i, j) of block M, where i may lie one row
+// beyond a periodic z face (its image) or a HALO face (the halo row's).
+template <class S>
+__device__ __forceinline__ Lag4 lag_at(const KParams &P, const char *M, int i, int j) {
+    const char *B = M;
+    long long plane = P.plane, off;
+    if ((unsigned)i >= (unsigned)P.Nz) {
+        const int f = i < 0 ? 0 : 1;
+        if (kind_of(P, Z_LO + f, FLOW) == HALO) {
+            B = P.halo_lag[f];
+            plane = P.pitch;
+            off = j;
+            return {lag_ld<S>(B, 0, plane, off), lag_ld<S>(B, 1, plane, off),
+                    lag_ld<S>(B, 2, plane, off), lag_ld<S>(B, 3, plane, off)};
+        }
+        i += i < 0 ? P.Nz : -P.Nz;
+    }
+    off = (long long)i * P.pitch + j;
+    return {lag_ld<S>(B, 0, plane, off), lag_ld<S>(B, 1, plane, off), lag_ld<S>(B, 2, plane, off),
+            lag_ld<S>(B, 3, plane, off)};
+}
+
+// The lagged fields at element offset m of block M (a fluid node).
+template <class S>
+__device__ __forceinline__ Lag4 lag_node(const KParams &P, const char *M, unsigned m) {
+    return {lag_ld<S>(M, 0, P.plane, m), lag_ld<S>(M, 1, P.plane, m), lag_ld<S>(M, 2, P.plane, m),
+            lag_ld<S>(M, 3, P.plane, m)};
+}
+
+// The lagged fields a node update stores, as a reader will load them.
+template <class S>
+__device__ __forceinline__ Lag4 lag_stored(float ux, float uy, float ut, float dT) {
+    return {lag_round<S>(0, ux), lag_round<S>(1, uy), lag_round<S>(2, ut), lag_round<S>(3, dT)};
+}
+
+// Offset of population Q of distribution FLD that node (i, j) reads from its
+// own slot in the AA even phase: the writer's lagged fields (see above).
+template <class S, int FLD, int Q>
+__device__ __forceinline__ float even_off(const KParams &P, const char *M, int i, int j) {
+    using L = Lat<FLD>;
+    constexpr int ex = L::ex(Q), ey = L::ey(Q);
+    int si = i - ex, sj = j - ey;
+    if ((unsigned)si < (unsigned)P.Nz && (unsigned)sj < (unsigned)P.Nr)
+        return pop_off<FLD>(Q, lag_at<S>(P, M, si, sj));
+    const int c2 = 2 * j - ey;
+    const int fy = sj < 0 ? R_IN : (sj >= P.Nr ? R_OUT : -1);
+    const int fx = si < 0 ? Z_LO : (si >= P.Nz ? Z_HI : -1);
+    if ((fy >= 0 && is_wall(kind_of(P, fy, FLD))) || (fx >= 0 && is_wall(kind_at(P, fx, FLD, c2))))
+        return pop_off<FLD>(L::opp(Q), lag_at<S>(P, M, i, j));
+    if (fy >= 0) sj = j;  // the axis
+    if (FLD == FLOW && fx >= 0 && kind_at(P, fx, FLOW, c2) == SLIP) si = i;
+    return pop_off<FLD>(Q, lag_at<S>(P, M, si, sj));  // a row beyond a periodic face: its image
+}
+
+// ----------------------------------------------------------------------------
 // Population sources for the pulls: src(p, i, j) is the value in plane p
 // (0..18) at node (i, j), where i may lie one row beyond a periodic z face
 // (the source then supplies the periodic image) or a HALO face.
 // GlobalPops reads a population buffer in device memory.
 // A row beyond a HALO z face comes from that face's halo row instead.
-template <class S>
+// ENC: offset-encoded storage whose writer is the node holding the slot,
+// with the lagged fields M; AA: planes hold the opposite direction (the
+// state the AA even phase leaves).
+template <class S, bool ENC = kEnc<S>, bool AA = false>
 struct GlobalPops {
     const KParams &P;
     const S *A;
+    const char *M;
     __device__ __forceinline__ float operator()(int p, int i, int j) const {
+        float v;
+        const int ri = i;
         if ((unsigned)i >= (unsigned)P.Nz) {
             const int f = i < 0 ? 0 : 1;
-            if (kind_of(P, Z_LO + f, FLOW) == HALO)
-                return Conv<S>::ld(static_cast<const S *>(P.halo_pop[f]) + p * P.pitch + j);
+            if (kind_of(P, Z_LO + f, FLOW) == HALO) {
+                v = Conv<S>::ld(static_cast<const S *>(P.halo_pop[f]) + p * P.pitch + j);
+                if constexpr (ENC) v = v + plane_off<AA>(p, lag_at<S>(P, M, ri, j));
+                return v;
+            }
             i += i < 0 ? P.Nz : -P.Nz;
         }
-        return Conv<S>::ld(A + p * P.plane + (long long)i * P.pitch + j);
+        v = Conv<S>::ld(A + p * P.plane + (long long)i * P.pitch + j);
+        if constexpr (ENC) v = v + plane_off<AA>(p, lag_at<S>(P, M, i, j));
+        return v;
     }
 };
 
@@ -233,10 +358,12 @@ __device__ __forceinline__ void pull_all(const KParams &P, const Src &src, int i
 }
 
 // Odd AA phase: post-collision f*_Q(i, j) = v goes to the slot from which
-// the next (even) phase reads it, by the same rules as pull_edge.
-template <class S, int FLD, int Q>
+// the next (even) phase reads it, by the same rules as pull_edge.  ENC
+// subtracts the offset of the node's own stored lagged fields Ln: for the
+// direction Q after a wall, for the direction of the receiving plane else.
+template <class S, int FLD, int Q, bool ENC = kEnc<S>>
 __device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, float v,
-                                          unsigned w0) {
+                                          unsigned w0, const Lag4 &Ln) {
     using L = Lat<FLD>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
     int ti = i + ex;
@@ -263,6 +390,7 @@ __device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, 
                 w = w + un * un * wall_raw<FLD>(P, wall, c2, ym);
             }
         }
+        if constexpr (ENC) w = w - pop_off<FLD>(Q, Ln);
         Conv<S>::st(A + (L::OFF + L::opp(Q)) * P.plane + (long long)i * P.pitch + j, w,
                     slot_word(w0, L::OFF + Q));
         return;
@@ -278,31 +406,40 @@ __device__ __forceinline__ void push_edge(const KParams &P, S *A, int i, int j, 
         } else if (ti >= P.Nz) {
             ti -= P.Nz;
         }
-        Conv<S>::st(A + (L::OFF + q) * P.plane + (long long)ti * P.pitch + j,
-                    FLD == SWIRL ? -v : v, slot_word(w0, L::OFF + Q));
+        float w = FLD == SWIRL ? -v : v;
+        if constexpr (ENC) w = w - pop_off<FLD>(q, Ln);
+        Conv<S>::st(A + (L::OFF + q) * P.plane + (long long)ti * P.pitch + j, w,
+                    slot_word(w0, L::OFF + Q));
         return;
     }
     if (slip) {  // free surface: arrives at (i, j + e_y) with e_x reversed
-        Conv<S>::st(A + (L::OFF + Lat<FLOW>::reflx(Q)) * P.plane + (long long)i * P.pitch + tj, v,
+        float w = v;
+        if constexpr (ENC) w = w - pop_off<FLOW>(Lat<FLOW>::reflx(Q), Ln);
+        Conv<S>::st(A + (L::OFF + Lat<FLOW>::reflx(Q)) * P.plane + (long long)i * P.pitch + tj, w,
                     slot_word(w0, L::OFF + Q));
         return;
     }
     ti += ti < 0 ? P.Nz : -P.Nz;  // periodic
-    Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, v,
+    float w = v;
+    if constexpr (ENC) w = w - pop_off<FLD>(Q, Ln);
+    Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, w,
                 slot_word(w0, L::OFF + Q));
 }
 
-template <class S, int FLD, int Q>
-__device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float v, unsigned w0) {
+template <class S, int FLD, int Q, bool ENC = kEnc<S>>
+__device__ __forceinline__ void push(const KParams &P, S *A, int i, int j, float v, unsigned w0,
+                                     const Lag4 &Ln) {
     using L = Lat<FLD>;
     constexpr int ex = L::ex(Q), ey = L::ey(Q);
     const int ti = i + ex, tj = j + ey;
     if ((unsigned)ti < (unsigned)P.Nz && (unsigned)tj < (unsigned)P.Nr) {
-        Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, v,
+        float w = v;
+        if constexpr (ENC) w = w - pop_off<FLD>(Q, Ln);
+        Conv<S>::st(A + (L::OFF + Q) * P.plane + (long long)ti * P.pitch + tj, w,
                     slot_word(w0, L::OFF + Q));
         return;
     }
-    push_edge<S, FLD, Q>(P, A, i, j, v, w0);
+    push_edge<S, FLD, Q, ENC>(P, A, i, j, v, w0, Ln);
 }
 
 // ----------------------------------------------------------------------------
@@ -576,13 +713,16 @@ __device__ __forceinline__ void tile_of(const KParams &P, int &i, int &j) {
 enum Mode { MODE_AB = 0, MODE_AA_ODD = 1, MODE_AA_EVEN = 2 };
 
 // Interior pull: the source node n - e_q is a fluid node (32-bit offsets
-// against a uniform plane base).
-template <class S, bool AA, int FLD, int Q>
-__device__ __forceinline__ float pull_in(const KParams &P, const S *A, unsigned n) {
+// against a uniform plane base).  With offset encoding the source node wrote
+// the slot, for direction Q in both slot conventions.
+template <class S, bool AA, int FLD, int Q, bool ENC = kEnc<S>>
+__device__ __forceinline__ float pull_in(const KParams &P, const S *A, const char *M, unsigned n) {
     using L = Lat<FLD>;
     constexpr int slot = AA ? L::opp(Q) : Q;
     const unsigned dn = (unsigned)(L::ex(Q) * P.pitch + L::ey(Q));
-    return Conv<S>::ld(A + (long long)(L::OFF + slot) * P.plane + (n - dn));
+    float v = Conv<S>::ld(A + (long long)(L::OFF + slot) * P.plane + (n - dn));
+    if constexpr (ENC) v = v + pop_off<FLD>(Q, lag_node<S>(P, M, n - dn));
+    return v;
 }
 
 template <class S, int FLD, int Q>
@@ -592,9 +732,66 @@ __device__ __forceinline__ void push_in(const KParams &P, S *A, unsigned n, floa
     Conv<S>::st(A + (long long)(L::OFF + Q) * P.plane + (n + dn), v, slot_word(w0, L::OFF + Q));
 }
 
-template <class S, int MODE>
-__device__ __forceinline__ void gather(const KParams &P, const S *A, int i, int j, bool interior,
-                                       float (&f)[9], float (&g)[5], float (&h)[5]) {
+// Offset decoding of the populations x of distribution FLD that node (i, j)
+// read from its own slots in the AA even phase (even_off per population).
+template <class S, int FLD, int N, int... Q>
+__device__ __forceinline__ void even_offsets(const KParams &P, const char *M, int i, int j,
+                                             float (&x)[N], std::integer_sequence<int, Q...>) {
+    ((x[Q] = x[Q] + even_off<S, FLD, Q>(P, M, i, j)), ...);
+}
+// The same where every source node n - e_q is a fluid node (n the node's
+// element offset): the writer of population q is n - e_q.
+template <class S, int FLD, int N, int... Q>
+__device__ __forceinline__ void link_offsets(const KParams &P, const char *M, unsigned n,
+                                             float (&x)[N], std::integer_sequence<int, Q...>) {
+    ((x[Q] = x[Q] + pop_off<FLD>(Q, lag_node<S>(P, M, n - (unsigned)(Lat<FLD>::ex(Q) * P.pitch +
+                                                                        Lat<FLD>::ey(Q))))),
+     ...);
+}
+template <class S>
+__device__ __forceinline__ void decode_even(const KParams &P, const char *M, int i, int j,
+                                            bool interior, float (&f)[9], float (&g)[5],
+                                            float (&h)[5]) {
+    if (interior) {
+        const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
+        link_offsets<S, FLOW>(P, M, n, f, std::make_integer_sequence<int, 9>{});
+        link_offsets<S, SWIRL>(P, M, n, g, std::make_integer_sequence<int, 5>{});
+        link_offsets<S, THERMAL>(P, M, n, h, std::make_integer_sequence<int, 5>{});
+    } else {
+        even_offsets<S, FLOW>(P, M, i, j, f, std::make_integer_sequence<int, 9>{});
+        even_offsets<S, SWIRL>(P, M, i, j, g, std::make_integer_sequence<int, 5>{});
+        even_offsets<S, THERMAL>(P, M, i, j, h, std::make_integer_sequence<int, 5>{});
+    }
+}
+
+// Post-collision populations as a node stores them: minus the offsets of
+// its own stored lagged fields Ln (direction q) with offset encoding.
+template <bool ENC>
+__device__ __forceinline__ void encode(const float (&f)[9], const float (&g)[5],
+                                       const float (&h)[5], const Lag4 &Ln, float (&ef)[9],
+                                       float (&eg)[5], float (&eh)[5]) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        ef[q] = f[q];
+        if constexpr (ENC) ef[q] = f[q] - pop_off<FLOW>(q, Ln);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        eg[q] = g[q];
+        eh[q] = h[q];
+        if constexpr (ENC) {
+            eg[q] = g[q] - pop_off<SWIRL>(q, Ln);
+            eh[q] = h[q] - pop_off<THERMAL>(q, Ln);
+        }
+    }
+}
+
+// The 19 populations node (i, j) streams in from state A (lagged fields M
+// of the same step), in slot convention MODE.
+template <class S, int MODE, bool ENC = kEnc<S>>
+__device__ __forceinline__ void gather(const KParams &P, const S *A, const char *M, int i, int j,
+                                       bool interior, float (&f)[9], float (&g)[5],
+                                       float (&h)[5]) {
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
     if (MODE == MODE_AA_EVEN) {
 #pragma unroll
@@ -604,100 +801,107 @@ __device__ __forceinline__ void gather(const KParams &P, const S *A, int i, int 
             g[q] = Conv<S>::ld(A + (long long)(GOFF + q) * P.plane + n);
             h[q] = Conv<S>::ld(A + (long long)(HOFF + q) * P.plane + n);
         }
+        if constexpr (ENC) decode_even<S>(P, M, i, j, interior, f, g, h);
         return;
     }
     constexpr bool AA = MODE == MODE_AA_ODD;
     if (interior) {
-        f[0] = pull_in<S, AA, FLOW, 0>(P, A, n);
-        f[1] = pull_in<S, AA, FLOW, 1>(P, A, n);
-        f[2] = pull_in<S, AA, FLOW, 2>(P, A, n);
-        f[3] = pull_in<S, AA, FLOW, 3>(P, A, n);
-        f[4] = pull_in<S, AA, FLOW, 4>(P, A, n);
-        f[5] = pull_in<S, AA, FLOW, 5>(P, A, n);
-        f[6] = pull_in<S, AA, FLOW, 6>(P, A, n);
-        f[7] = pull_in<S, AA, FLOW, 7>(P, A, n);
-        f[8] = pull_in<S, AA, FLOW, 8>(P, A, n);
-        g[0] = pull_in<S, AA, SWIRL, 0>(P, A, n);
-        g[1] = pull_in<S, AA, SWIRL, 1>(P, A, n);
-        g[2] = pull_in<S, AA, SWIRL, 2>(P, A, n);
-        g[3] = pull_in<S, AA, SWIRL, 3>(P, A, n);
-        g[4] = pull_in<S, AA, SWIRL, 4>(P, A, n);
-        h[0] = pull_in<S, AA, THERMAL, 0>(P, A, n);
-        h[1] = pull_in<S, AA, THERMAL, 1>(P, A, n);
-        h[2] = pull_in<S, AA, THERMAL, 2>(P, A, n);
-        h[3] = pull_in<S, AA, THERMAL, 3>(P, A, n);
-        h[4] = pull_in<S, AA, THERMAL, 4>(P, A, n);
+        f[0] = pull_in<S, AA, FLOW, 0, ENC>(P, A, M, n);
+        f[1] = pull_in<S, AA, FLOW, 1, ENC>(P, A, M, n);
+        f[2] = pull_in<S, AA, FLOW, 2, ENC>(P, A, M, n);
+        f[3] = pull_in<S, AA, FLOW, 3, ENC>(P, A, M, n);
+        f[4] = pull_in<S, AA, FLOW, 4, ENC>(P, A, M, n);
+        f[5] = pull_in<S, AA, FLOW, 5, ENC>(P, A, M, n);
+        f[6] = pull_in<S, AA, FLOW, 6, ENC>(P, A, M, n);
+        f[7] = pull_in<S, AA, FLOW, 7, ENC>(P, A, M, n);
+        f[8] = pull_in<S, AA, FLOW, 8, ENC>(P, A, M, n);
+        g[0] = pull_in<S, AA, SWIRL, 0, ENC>(P, A, M, n);
+        g[1] = pull_in<S, AA, SWIRL, 1, ENC>(P, A, M, n);
+        g[2] = pull_in<S, AA, SWIRL, 2, ENC>(P, A, M, n);
+        g[3] = pull_in<S, AA, SWIRL, 3, ENC>(P, A, M, n);
+        g[4] = pull_in<S, AA, SWIRL, 4, ENC>(P, A, M, n);
+        h[0] = pull_in<S, AA, THERMAL, 0, ENC>(P, A, M, n);
+        h[1] = pull_in<S, AA, THERMAL, 1, ENC>(P, A, M, n);
+        h[2] = pull_in<S, AA, THERMAL, 2, ENC>(P, A, M, n);
+        h[3] = pull_in<S, AA, THERMAL, 3, ENC>(P, A, M, n);
+        h[4] = pull_in<S, AA, THERMAL, 4, ENC>(P, A, M, n);
         return;
     }
-    pull_all<AA>(P, GlobalPops<S>{P, A}, i, j, f, g, h);
+    pull_all<AA>(P, GlobalPops<S, ENC, AA>{P, A, M}, i, j, f, g, h);
 }
 
-template <class S, int MODE>
+// Stores the post-collision populations of node (i, j) in slot convention
+// MODE; Ln: the node's lagged fields as stored (offset encoding).
+template <class S, int MODE, bool ENC = kEnc<S>>
 __device__ __forceinline__ void scatter(const KParams &P, S *A, int i, int j, bool interior,
                                         const float (&f)[9], const float (&g)[5],
-                                        const float (&h)[5]) {
+                                        const float (&h)[5], const Lag4 &Ln) {
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
-    const unsigned w0 = node_word(f, g, h, i, j);
+    const unsigned w0 = node_word(f, g, h, i + P.row0, j);
+    if (MODE == MODE_AA_ODD && !interior) {
+        push<S, FLOW, 0, ENC>(P, A, i, j, f[0], w0, Ln);
+        push<S, FLOW, 1, ENC>(P, A, i, j, f[1], w0, Ln);
+        push<S, FLOW, 2, ENC>(P, A, i, j, f[2], w0, Ln);
+        push<S, FLOW, 3, ENC>(P, A, i, j, f[3], w0, Ln);
+        push<S, FLOW, 4, ENC>(P, A, i, j, f[4], w0, Ln);
+        push<S, FLOW, 5, ENC>(P, A, i, j, f[5], w0, Ln);
+        push<S, FLOW, 6, ENC>(P, A, i, j, f[6], w0, Ln);
+        push<S, FLOW, 7, ENC>(P, A, i, j, f[7], w0, Ln);
+        push<S, FLOW, 8, ENC>(P, A, i, j, f[8], w0, Ln);
+        push<S, SWIRL, 0, ENC>(P, A, i, j, g[0], w0, Ln);
+        push<S, SWIRL, 1, ENC>(P, A, i, j, g[1], w0, Ln);
+        push<S, SWIRL, 2, ENC>(P, A, i, j, g[2], w0, Ln);
+        push<S, SWIRL, 3, ENC>(P, A, i, j, g[3], w0, Ln);
+        push<S, SWIRL, 4, ENC>(P, A, i, j, g[4], w0, Ln);
+        push<S, THERMAL, 0, ENC>(P, A, i, j, h[0], w0, Ln);
+        push<S, THERMAL, 1, ENC>(P, A, i, j, h[1], w0, Ln);
+        push<S, THERMAL, 2, ENC>(P, A, i, j, h[2], w0, Ln);
+        push<S, THERMAL, 3, ENC>(P, A, i, j, h[3], w0, Ln);
+        push<S, THERMAL, 4, ENC>(P, A, i, j, h[4], w0, Ln);
+        return;
+    }
+    float ef[9], eg[5], eh[5];
+    encode<ENC>(f, g, h, Ln, ef, eg, eh);
     if (MODE == MODE_AB) {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            Conv<S>::st(A + (long long)q * P.plane + n, f[q], slot_word(w0, q));
+            Conv<S>::st(A + (long long)q * P.plane + n, ef[q], slot_word(w0, q));
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            Conv<S>::st(A + (long long)(GOFF + q) * P.plane + n, g[q], slot_word(w0, GOFF + q));
-            Conv<S>::st(A + (long long)(HOFF + q) * P.plane + n, h[q], slot_word(w0, HOFF + q));
+            Conv<S>::st(A + (long long)(GOFF + q) * P.plane + n, eg[q], slot_word(w0, GOFF + q));
+            Conv<S>::st(A + (long long)(HOFF + q) * P.plane + n, eh[q], slot_word(w0, HOFF + q));
         }
     } else if (MODE == MODE_AA_EVEN) {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            Conv<S>::st(A + (long long)Lat<FLOW>::opp(q) * P.plane + n, f[q], slot_word(w0, q));
+            Conv<S>::st(A + (long long)Lat<FLOW>::opp(q) * P.plane + n, ef[q], slot_word(w0, q));
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            Conv<S>::st(A + (long long)(GOFF + Lat<SWIRL>::opp(q)) * P.plane + n, g[q],
+            Conv<S>::st(A + (long long)(GOFF + Lat<SWIRL>::opp(q)) * P.plane + n, eg[q],
                         slot_word(w0, GOFF + q));
-            Conv<S>::st(A + (long long)(HOFF + Lat<THERMAL>::opp(q)) * P.plane + n, h[q],
+            Conv<S>::st(A + (long long)(HOFF + Lat<THERMAL>::opp(q)) * P.plane + n, eh[q],
                         slot_word(w0, HOFF + q));
         }
-    } else if (interior) {
-        push_in<S, FLOW, 0>(P, A, n, f[0], w0);
-        push_in<S, FLOW, 1>(P, A, n, f[1], w0);
-        push_in<S, FLOW, 2>(P, A, n, f[2], w0);
-        push_in<S, FLOW, 3>(P, A, n, f[3], w0);
-        push_in<S, FLOW, 4>(P, A, n, f[4], w0);
-        push_in<S, FLOW, 5>(P, A, n, f[5], w0);
-        push_in<S, FLOW, 6>(P, A, n, f[6], w0);
-        push_in<S, FLOW, 7>(P, A, n, f[7], w0);
-        push_in<S, FLOW, 8>(P, A, n, f[8], w0);
-        push_in<S, SWIRL, 0>(P, A, n, g[0], w0);
-        push_in<S, SWIRL, 1>(P, A, n, g[1], w0);
-        push_in<S, SWIRL, 2>(P, A, n, g[2], w0);
-        push_in<S, SWIRL, 3>(P, A, n, g[3], w0);
-        push_in<S, SWIRL, 4>(P, A, n, g[4], w0);
-        push_in<S, THERMAL, 0>(P, A, n, h[0], w0);
-        push_in<S, THERMAL, 1>(P, A, n, h[1], w0);
-        push_in<S, THERMAL, 2>(P, A, n, h[2], w0);
-        push_in<S, THERMAL, 3>(P, A, n, h[3], w0);
-        push_in<S, THERMAL, 4>(P, A, n, h[4], w0);
     } else {
-        push<S, FLOW, 0>(P, A, i, j, f[0], w0);
-        push<S, FLOW, 1>(P, A, i, j, f[1], w0);
-        push<S, FLOW, 2>(P, A, i, j, f[2], w0);
-        push<S, FLOW, 3>(P, A, i, j, f[3], w0);
-        push<S, FLOW, 4>(P, A, i, j, f[4], w0);
-        push<S, FLOW, 5>(P, A, i, j, f[5], w0);
-        push<S, FLOW, 6>(P, A, i, j, f[6], w0);
-        push<S, FLOW, 7>(P, A, i, j, f[7], w0);
-        push<S, FLOW, 8>(P, A, i, j, f[8], w0);
-        push<S, SWIRL, 0>(P, A, i, j, g[0], w0);
-        push<S, SWIRL, 1>(P, A, i, j, g[1], w0);
-        push<S, SWIRL, 2>(P, A, i, j, g[2], w0);
-        push<S, SWIRL, 3>(P, A, i, j, g[3], w0);
-        push<S, SWIRL, 4>(P, A, i, j, g[4], w0);
-        push<S, THERMAL, 0>(P, A, i, j, h[0], w0);
-        push<S, THERMAL, 1>(P, A, i, j, h[1], w0);
-        push<S, THERMAL, 2>(P, A, i, j, h[2], w0);
-        push<S, THERMAL, 3>(P, A, i, j, h[3], w0);
-        push<S, THERMAL, 4>(P, A, i, j, h[4], w0);
+        push_in<S, FLOW, 0>(P, A, n, ef[0], w0);
+        push_in<S, FLOW, 1>(P, A, n, ef[1], w0);
+        push_in<S, FLOW, 2>(P, A, n, ef[2], w0);
+        push_in<S, FLOW, 3>(P, A, n, ef[3], w0);
+        push_in<S, FLOW, 4>(P, A, n, ef[4], w0);
+        push_in<S, FLOW, 5>(P, A, n, ef[5], w0);
+        push_in<S, FLOW, 6>(P, A, n, ef[6], w0);
+        push_in<S, FLOW, 7>(P, A, n, ef[7], w0);
+        push_in<S, FLOW, 8>(P, A, n, ef[8], w0);
+        push_in<S, SWIRL, 0>(P, A, n, eg[0], w0);
+        push_in<S, SWIRL, 1>(P, A, n, eg[1], w0);
+        push_in<S, SWIRL, 2>(P, A, n, eg[2], w0);
+        push_in<S, SWIRL, 3>(P, A, n, eg[3], w0);
+        push_in<S, SWIRL, 4>(P, A, n, eg[4], w0);
+        push_in<S, THERMAL, 0>(P, A, n, eh[0], w0);
+        push_in<S, THERMAL, 1>(P, A, n, eh[1], w0);
+        push_in<S, THERMAL, 2>(P, A, n, eh[2], w0);
+        push_in<S, THERMAL, 3>(P, A, n, eh[3], w0);
+        push_in<S, THERMAL, 4>(P, A, n, eh[4], w0);
     }
 }
 
@@ -759,11 +963,12 @@ __device__ __forceinline__ void update_node(const KParams &P, const S *src, S *d
                                             char *__restrict__ Mnext, int i, int j,
                                             bool interior) {
     float f[9], g[5], h[5];
-    gather<S, MODE>(P, src, i, j, interior, f, g, h);
+    gather<S, MODE>(P, src, Mprev, i, j, interior, f, g, h);
     float d[5];
     derivatives<S>(P, Mprev, i, j, interior, d);
     const Half H = relax_node(P, j, f, g, h, d);
-    scatter<S, MODE>(P, dst, i, j, interior, f, g, h);
+    scatter<S, MODE>(P, dst, i, j, interior, f, g, h,
+                     lag_stored<S>(H.ux, H.uy, H.psi * H.irho, H.dphi));
     const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
     lag_st<S>(Mnext, 0, P.plane, n, H.ux);
     lag_st<S>(Mnext, 1, P.plane, n, H.uy);
@@ -819,19 +1024,49 @@ __device__ __forceinline__ void gather_planes(const Planes &A, unsigned o, float
         h[q] = ld_plane<S>(A.rd[HOFF + q], o);
     }
 }
-template <class S>
-__device__ __forceinline__ void scatter_planes(const Planes &A, unsigned o, int i, int j,
+// Ln: the node's lagged fields as stored (offset encoding); gi: the node's
+// global row (rounding key).
+template <class S, bool ENC = kEnc<S>>
+__device__ __forceinline__ void scatter_planes(const Planes &A, unsigned o, int gi, int j,
                                                const float (&f)[9], const float (&g)[5],
-                                               const float (&h)[5]) {
+                                               const float (&h)[5], const Lag4 &Ln) {
     typename Conv<S>::Reg r{};
-    const unsigned w0 = node_word(f, g, h, i, j);
+    const unsigned w0 = node_word(f, g, h, gi, j);
+    float ef[9], eg[5], eh[5];
+    encode<ENC>(f, g, h, Ln, ef, eg, eh);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], o, f[q], slot_word(w0, q), r);
+    for (int q = 0; q < 9; ++q) st_plane<S>(A.wr[q], o, ef[q], slot_word(w0, q), r);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-        st_plane<S>(A.wr[GOFF + q], o, g[q], slot_word(w0, GOFF + q), r);
-        st_plane<S>(A.wr[HOFF + q], o, h[q], slot_word(w0, HOFF + q), r);
+        st_plane<S>(A.wr[GOFF + q], o, eg[q], slot_word(w0, GOFF + q), r);
+        st_plane<S>(A.wr[HOFF + q], o, eh[q], slot_word(w0, HOFF + q), r);
     }
+}
+
+// Offset decoding of populations gathered through plane addresses where
+// every source node n - e_q is a fluid node (n: the node's element offset):
+// the writer's lagged fields through the launch's lagged-field planes, the
+// values lag_node gives.
+template <class S>
+__device__ __forceinline__ Lag4 lag_planes(const Planes &A, unsigned m) {
+    using F = LagFmt<S>;
+    return {lag_plane<S>(A.lrd[0], m * F::VB), lag_plane<S>(A.lrd[1], m * F::VB),
+            lag_plane<S>(A.lrd[2], m * F::VB), gload<float>(A.lrd[3], m * 4u)};
+}
+template <class S, int FLD, int N, int... Q>
+__device__ __forceinline__ void link_offsets_planes(const KParams &P, const Planes &A, unsigned n,
+                                                    float (&x)[N],
+                                                    std::integer_sequence<int, Q...>) {
+    ((x[Q] = x[Q] + pop_off<FLD>(Q, lag_planes<S>(A, n - (unsigned)(Lat<FLD>::ex(Q) * P.pitch +
+                                                                     Lat<FLD>::ey(Q))))),
+     ...);
+}
+template <class S>
+__device__ __forceinline__ void decode_planes(const KParams &P, const Planes &A, unsigned n,
+                                              float (&f)[9], float (&g)[5], float (&h)[5]) {
+    link_offsets_planes<S, FLOW>(P, A, n, f, std::make_integer_sequence<int, 9>{});
+    link_offsets_planes<S, SWIRL>(P, A, n, g, std::make_integer_sequence<int, 5>{});
+    link_offsets_planes<S, THERMAL>(P, A, n, h, std::make_integer_sequence<int, 5>{});
 }
 // A register copy of a byte offset that the compiler cannot trace back to
 // an earlier basic block: it chooses the SGPR-base address form per block,
@@ -856,6 +1091,11 @@ __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A,
     const unsigned o = n * (unsigned)sizeof(S), ov = n * VB, o4 = n * 4u;
     float f[9], g[5], h[5];
     gather_planes<S>(A, o, f, g, h);
+    if constexpr (kEnc<S>) {
+        // edge nodes come here in the AA even phase only
+        if (interior) decode_planes<S>(P, A, n, f, g, h);
+        else decode_even<S>(P, A.lrd[0], i, j, false, f, g, h);
+    }
     float d[5];
     if (interior) {
         d[0] = 0.5f * (lag_plane<S>(A.uy_up, ov) - lag_plane<S>(A.uy_dn, ov));
@@ -869,7 +1109,8 @@ __device__ __forceinline__ void update_planes(const KParams &P, const Planes &A,
     const Half H = relax_node(P, j, f, g, h, d);
     // the stores follow the branch above
     const unsigned so = local_offset(o), sov = local_offset(ov), so4 = local_offset(o4);
-    scatter_planes<S>(A, so, i, j, f, g, h);
+    scatter_planes<S>(A, so, i + P.row0, j, f, g, h,
+                      lag_stored<S>(H.ux, H.uy, H.psi * H.irho, H.dphi));
     gstore(A.lwr[0], sov, F::enc(H.ux));
     gstore(A.lwr[1], sov, F::enc(H.uy));
     gstore(A.lwr[2], sov, F::enc(H.psi * H.irho));

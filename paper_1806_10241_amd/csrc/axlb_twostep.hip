@@ -35,47 +35,60 @@ constexpr int TWO_TW = TWO_CW - 2, TWO_TH = TWO_CH - 2;
 constexpr int BATCH_CH = 16, BATCH_TH = BATCH_CH - 2;
 
 // The LDS block of post-collision populations as a population source for
-// pull_all: node (i, j) sits in cell (i - i0 + 1, j - j0 + 1).
+// pull_all: node (i, j) sits in cell (i - i0 + 1, j - j0 + 1).  With offset
+// encoding the cell's own lagged fields (LDS block Lg) decode its slots.
 template <class S, int H, int W>
 struct TilePops {
     const S (&A)[NPOP][H][W];
+    const float (&Lg)[NLAG][H][W];
     int i0, j0;
     __device__ __forceinline__ float operator()(int p, int i, int j) const {
-        return Conv<S>::ld(&A[p][i - i0 + 1][j - j0 + 1]);
+        const int a = i - i0 + 1, b = j - j0 + 1;
+        float v = Conv<S>::ld(&A[p][a][b]);
+        if constexpr (kEnc<S>)
+            v = v + plane_off<false>(p, Lag4{Lg[0][a][b], Lg[1][a][b], Lg[2][a][b], Lg[3][a][b]});
+        return v;
     }
 };
 
 // Pull of population Q of distribution FLD from the LDS block for an
 // interior node in cell (a, b): the post-collision value of the neighbour
-// x - e_Q (two-buffer convention, plane Q).
+// x - e_Q (two-buffer convention, plane Q), decoded with that neighbour's
+// lagged fields.
 template <class S, int FLD, int Q, int H, int W>
-__device__ __forceinline__ float pull_lds(const S (&A)[NPOP][H][W], int a, int b) {
+__device__ __forceinline__ float pull_lds(const S (&A)[NPOP][H][W], const float (&Lg)[NLAG][H][W],
+                                          int a, int b) {
     using L = Lat<FLD>;
-    return Conv<S>::ld(&A[L::OFF + Q][a - L::ex(Q)][b - L::ey(Q)]);
+    const int sa = a - L::ex(Q), sb = b - L::ey(Q);
+    float v = Conv<S>::ld(&A[L::OFF + Q][sa][sb]);
+    if constexpr (kEnc<S>)
+        v = v + pop_off<FLD>(Q, Lag4{Lg[0][sa][sb], Lg[1][sa][sb], Lg[2][sa][sb], Lg[3][sa][sb]});
+    return v;
 }
 
 template <class S, int H, int W>
-__device__ __forceinline__ void pull_lds_all(const S (&A)[NPOP][H][W], int a, int b,
+__device__ __forceinline__ void pull_lds_all(const S (&A)[NPOP][H][W],
+                                             const float (&Lg)[NLAG][H][W], int a, int b,
                                              float (&f)[9], float (&g)[5], float (&h)[5]) {
-    f[0] = pull_lds<S, FLOW, 0>(A, a, b);
-    f[1] = pull_lds<S, FLOW, 1>(A, a, b);
-    f[2] = pull_lds<S, FLOW, 2>(A, a, b);
-    f[3] = pull_lds<S, FLOW, 3>(A, a, b);
-    f[4] = pull_lds<S, FLOW, 4>(A, a, b);
-    f[5] = pull_lds<S, FLOW, 5>(A, a, b);
-    f[6] = pull_lds<S, FLOW, 6>(A, a, b);
-    f[7] = pull_lds<S, FLOW, 7>(A, a, b);
-    f[8] = pull_lds<S, FLOW, 8>(A, a, b);
-    g[0] = pull_lds<S, SWIRL, 0>(A, a, b);
-    g[1] = pull_lds<S, SWIRL, 1>(A, a, b);
-    g[2] = pull_lds<S, SWIRL, 2>(A, a, b);
-    g[3] = pull_lds<S, SWIRL, 3>(A, a, b);
-    g[4] = pull_lds<S, SWIRL, 4>(A, a, b);
-    h[0] = pull_lds<S, THERMAL, 0>(A, a, b);
-    h[1] = pull_lds<S, THERMAL, 1>(A, a, b);
-    h[2] = pull_lds<S, THERMAL, 2>(A, a, b);
-    h[3] = pull_lds<S, THERMAL, 3>(A, a, b);
-    h[4] = pull_lds<S, THERMAL, 4>(A, a, b);
+    f[0] = pull_lds<S, FLOW, 0>(A, Lg, a, b);
+    f[1] = pull_lds<S, FLOW, 1>(A, Lg, a, b);
+    f[2] = pull_lds<S, FLOW, 2>(A, Lg, a, b);
+    f[3] = pull_lds<S, FLOW, 3>(A, Lg, a, b);
+    f[4] = pull_lds<S, FLOW, 4>(A, Lg, a, b);
+    f[5] = pull_lds<S, FLOW, 5>(A, Lg, a, b);
+    f[6] = pull_lds<S, FLOW, 6>(A, Lg, a, b);
+    f[7] = pull_lds<S, FLOW, 7>(A, Lg, a, b);
+    f[8] = pull_lds<S, FLOW, 8>(A, Lg, a, b);
+    g[0] = pull_lds<S, SWIRL, 0>(A, Lg, a, b);
+    g[1] = pull_lds<S, SWIRL, 1>(A, Lg, a, b);
+    g[2] = pull_lds<S, SWIRL, 2>(A, Lg, a, b);
+    g[3] = pull_lds<S, SWIRL, 3>(A, Lg, a, b);
+    g[4] = pull_lds<S, SWIRL, 4>(A, Lg, a, b);
+    h[0] = pull_lds<S, THERMAL, 0>(A, Lg, a, b);
+    h[1] = pull_lds<S, THERMAL, 1>(A, Lg, a, b);
+    h[2] = pull_lds<S, THERMAL, 2>(A, Lg, a, b);
+    h[3] = pull_lds<S, THERMAL, 3>(A, Lg, a, b);
+    h[4] = pull_lds<S, THERMAL, 4>(A, Lg, a, b);
 }
 
 // Two steps of the tile whose first node is (i0, j0), with the workgroup's
@@ -106,25 +119,30 @@ __device__ __forceinline__ void step_two_tile(const KParams &P, const Planes &A,
         if (live) {
             const bool interior = interior_node(P, ci, cj);
             float f[9], g[5], h[5], d[5];
-            if (interior)
-                gather_planes<S>(A, ((unsigned)ci * (unsigned)P.pitch + (unsigned)cj) *
-                                        (unsigned)sizeof(S), f, g, h);
-            else
-                gather<S, MODE_AB>(P, src, ci, cj, false, f, g, h);
+            if (interior) {
+                const unsigned cn = (unsigned)ci * (unsigned)P.pitch + (unsigned)cj;
+                gather_planes<S>(A, cn * (unsigned)sizeof(S), f, g, h);
+                if constexpr (kEnc<S>) decode_planes<S>(P, A, cn, f, g, h);
+            } else {
+                gather<S, MODE_AB>(P, src, Mprev, ci, cj, false, f, g, h);
+            }
             derivatives<S>(P, Mprev, ci, cj, interior, d);
             const Half Hs = relax_node(P, cj, f, g, h, d);
-            const unsigned w0 = node_word(f, g, h, ci, cj);
+            const unsigned w0 = node_word(f, g, h, ci + P.row0, cj);
+            const Lag4 Ln = lag_stored<S>(Hs.ux, Hs.uy, Hs.psi * Hs.irho, Hs.dphi);
+            float ef[9], eg[5], eh[5];
+            encode<kEnc<S>>(f, g, h, Ln, ef, eg, eh);
 #pragma unroll
-            for (int p = 0; p < 9; ++p) Conv<S>::st(&pop[p][a][b], f[p], slot_word(w0, p));
+            for (int p = 0; p < 9; ++p) Conv<S>::st(&pop[p][a][b], ef[p], slot_word(w0, p));
 #pragma unroll
             for (int p = 0; p < 5; ++p) {
-                Conv<S>::st(&pop[GOFF + p][a][b], g[p], slot_word(w0, GOFF + p));
-                Conv<S>::st(&pop[HOFF + p][a][b], h[p], slot_word(w0, HOFF + p));
+                Conv<S>::st(&pop[GOFF + p][a][b], eg[p], slot_word(w0, GOFF + p));
+                Conv<S>::st(&pop[HOFF + p][a][b], eh[p], slot_word(w0, HOFF + p));
             }
-            lag[0][a][b] = lag_round<S>(0, Hs.ux);
-            lag[1][a][b] = lag_round<S>(1, Hs.uy);
-            lag[2][a][b] = lag_round<S>(2, Hs.psi * Hs.irho);
-            lag[3][a][b] = lag_round<S>(3, Hs.dphi);
+            lag[0][a][b] = Ln.ux;
+            lag[1][a][b] = Ln.uy;
+            lag[2][a][b] = Ln.ut;
+            lag[3][a][b] = Ln.dT;
         }
     }
     __syncthreads();
@@ -134,14 +152,14 @@ __device__ __forceinline__ void step_two_tile(const KParams &P, const Planes &A,
     if (a >= 1 && a <= TH && b >= 1 && b <= TWO_TW && i < P.Nz && j < P.Nr) {
         float f[9], g[5], h[5], d[5];
         if (interior_node(P, i, j)) {
-            pull_lds_all<S>(pop, a, b, f, g, h);
+            pull_lds_all<S>(pop, lag, a, b, f, g, h);
             d[0] = 0.5f * (lag[1][a + 1][b] - lag[1][a - 1][b]);
             d[1] = 0.5f * (lag[0][a][b + 1] - lag[0][a][b - 1]);
             d[2] = 0.5f * (lag[1][a][b + 1] - lag[1][a][b - 1]);
             d[3] = 0.5f * (lag[2][a][b + 1] - lag[2][a][b - 1]);
             d[4] = 0.5f * (lag[3][a][b + 1] - lag[3][a][b - 1]);
         } else {
-            pull_all<false>(P, TilePops<S, H, W>{pop, i0, j0}, i, j, f, g, h);
+            pull_all<false>(P, TilePops<S, H, W>{pop, lag, i0, j0}, i, j, f, g, h);
             differences(P, TileSource<H, W>{lag, a, b}, i, j, d);
         }
         const Half Hs = relax_node(P, j, f, g, h, d);
@@ -149,7 +167,8 @@ __device__ __forceinline__ void step_two_tile(const KParams &P, const Planes &A,
         const unsigned n = (unsigned)i * (unsigned)P.pitch + (unsigned)j;
         const unsigned so = local_offset(n * (unsigned)sizeof(S)), sov = local_offset(n * F::VB);
         const unsigned so4 = local_offset(n * 4u);
-        scatter_planes<S>(A, so, i, j, f, g, h);
+        scatter_planes<S>(A, so, i + P.row0, j, f, g, h,
+                          lag_stored<S>(Hs.ux, Hs.uy, Hs.psi * Hs.irho, Hs.dphi));
         gstore(A.lwr[0], sov, F::enc(Hs.ux));
         gstore(A.lwr[1], sov, F::enc(Hs.uy));
         gstore(A.lwr[2], sov, F::enc(Hs.psi * Hs.irho));

@@ -36,7 +36,8 @@ def oracle_runs(orc):
 
 @pytest.mark.parametrize("layout,storage,deriv", [
     ("aa", "f32", "lagged"), ("ab", "f32", "lagged"), ("ab2", "f32", "lagged"),
-    ("ab", "f32", "current"), ("aa", "f16", "lagged")])
+    ("ab", "f32", "current"), ("aa", "f16", "lagged"), ("aa", "bf16", "lagged"),
+    ("ab2", "bf16", "lagged")])
 def test_czochralski_parity(gpu, orc, oracle_runs, layout, storage, deriv):
     say("czochralski parity", layout, storage, deriv)
     from paper_1806_10241_amd import axlb

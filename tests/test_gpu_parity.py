@@ -28,9 +28,6 @@ TOL = {"f32": 1e-5, "f16": 2e-3, "bf16": 2e-3}
 NU_TOL = 5e-3
 # per-node bar: MAX_FACTOR * (L2 bar) * (largest value of the field's scale)
 MAX_FACTOR = 30.0
-BF16_XFAIL = pytest.mark.xfail(
-    strict=False, reason="bfloat16 storage keeps 8 significant bits: measured field errors "
-    "2e-3 to 4e-3 and Nusselt errors up to 2% after 1000 steps, above the 2e-3 / 0.5% bars")
 # rho - 1 is a small difference of O(1) numbers: rounding every stored
 # population to FP32 (relative 2^-24) random-walks the density by about
 # 3 * 2^-24 * |f - w| per step, which after 1000 steps reaches ~1e-4 of
@@ -169,10 +166,10 @@ def test_fp32_parity(gpu, oracle_runs, name, layout):
             assert abs(x - y) <= NU_TOL * abs(y), (nu, nu_ref)
 
 
-def _16bit_parity(oracle_runs, name, storage):
-    say("parity", storage, name)
+def _16bit_parity(oracle_runs, name, storage, layout="aa"):
+    say("parity", storage, name, layout)
     ref, nu_ref = oracle_runs(name)
-    lat, F = run_gpu(CASES[name](), storage, "aa")
+    lat, F = run_gpu(CASES[name](), storage, layout)
     errs = field_errors(F, ref)
     nu = lat.nusselt()
     say("  errors", {k: "%.2e" % v[0] for k, v in errs.items()},
@@ -188,10 +185,13 @@ def test_f16_storage_parity(gpu, oracle_runs, name):
     _16bit_parity(oracle_runs, name, "f16")
 
 
-@BF16_XFAIL
+@pytest.mark.parametrize("layout", ["aa", "ab"])
 @pytest.mark.parametrize("name", ["c2", "c3"])
-def test_bf16_storage_parity(gpu, oracle_runs, name):
-    _16bit_parity(oracle_runs, name, "bf16")
+def test_bf16_storage_parity(gpu, oracle_runs, name, layout):
+    """bfloat16 keeps 8 significant bits: its slots hold each population
+    minus the linear equilibrium part of its writer's lagged fields, and meet
+    the binary16 bars with it."""
+    _16bit_parity(oracle_runs, name, "bf16", layout)
 
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c3"])
@@ -238,7 +238,7 @@ def test_graph_tails_equal_single_launches(gpu, layout):
     assert a.save() == b.save()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_checkpoint_resume_is_bitwise(gpu, storage):
     say("checkpoint", storage)
     from paper_1806_10241_amd import axlb
@@ -255,6 +255,27 @@ def test_checkpoint_resume_is_bitwise(gpu, storage):
     fa, fb = a.fields(), b.fields()
     for k in FIELDS:
         assert np.array_equal(fa[k], fb[k])
+
+
+def test_bf16_images_name_their_encoding(gpu):
+    """Offset-encoded bfloat16 populations mean something only with their
+    lagged fields: a lattice with current-step derivatives (plain bfloat16)
+    refuses such an image and the other way round, while plain storage
+    moves between the derivative forms."""
+    say("bf16 image encodings")
+    from paper_1806_10241_amd import axlb
+    c = c2_case()
+    a = axlb.Lattice(c, storage="bf16", layout="ab")
+    b = axlb.Lattice(c, storage="bf16", layout="ab", deriv="current")
+    a.step(3)
+    b.step(3)
+    with pytest.raises(axlb.AxlbError):
+        b.load(a.save())
+    with pytest.raises(axlb.AxlbError):
+        a.load(b.save())
+    f = axlb.Lattice(c, storage="f16", layout="ab", deriv="current")
+    f.load(axlb.Lattice(c, storage="f16", layout="ab").save())
+    assert f.steps == 0
 
 
 def smooth_fields(Nz, Nr, seed):
@@ -402,7 +423,7 @@ def test_autotune_restores_the_state(gpu):
     assert a.save() == b.save()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 @pytest.mark.parametrize("name", ["c1", "c2", "c3"])
 def test_two_step_launches_equal_single_steps_bitwise(gpu, name, storage):
     """Two steps per launch (tile and ring in LDS) against one step per
@@ -503,8 +524,7 @@ def steady_annulus(orc):
     return c, steps, L.nusselt()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16",
-                                     pytest.param("bf16", marks=BF16_XFAIL)])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_steady_nusselt_matches_the_oracle(gpu, steady_annulus, storage):
     """Steady wall Nusselt numbers with each storage against the oracle's:
     16-bit rounding that correlated with the values would bias them here

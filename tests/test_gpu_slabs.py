@@ -3,7 +3,9 @@ would be: each slab is a lattice of its own whose cut faces are HALO faces,
 and before every step each slab's boundary rows are packed
 (axlb_halo_export), moved (here a device copy, between GPUs a send and a
 receive) and unpacked into the neighbours' halos (axlb_halo_import).  The
-slabs must reproduce the uncut lattice bit for bit (FP32, two buffers)."""
+slabs must reproduce the uncut lattice bit for bit (two buffers; FP32, and
+bfloat16, whose offset-encoded halo populations decode with the halo row's
+lagged fields and whose rounding keys take each slab's global row 0)."""
 import copy
 
 import numpy as np
@@ -49,9 +51,10 @@ def exchange(torch, slabs, bufs, periodic):
         lat.sync()
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
 @pytest.mark.parametrize("name", ["lid", "annulus", "periodic"])
-def test_slabs_reproduce_the_uncut_lattice(gpu, name):
-    say("slabs", name)
+def test_slabs_reproduce_the_uncut_lattice(gpu, name, storage):
+    say("slabs", name, storage)
     from paper_1806_10241_amd import axlb
     torch = gpu
     if name == "lid":
@@ -62,12 +65,13 @@ def test_slabs_reproduce_the_uncut_lattice(gpu, name):
         case, rows = I.couette_poiseuille_conduction(Nr=70, Nz=18, r_inner=20.0, u_wall=0.02,
                                                      g=2e-5), [6, 5, 7]
     init = smooth_fields(case["Nz"], case["Nr"], 3)
-    full = axlb.Lattice(case, layout="ab", init_fields=False)
+    full = axlb.Lattice(case, storage=storage, layout="ab", init_fields=False)
     full.set_fields(**init)
     periodic = case["bc"][(I.Z_LO, I.FLOW)][0] == I.PERIODIC
-    slabs = []
-    for c, f in slab_cases(case, init, rows):
-        lat = axlb.Lattice(c, layout="ab", init_fields=False)
+    slabs, i0 = [], 0
+    for (c, f), n in zip(slab_cases(case, init, rows), rows):
+        lat = axlb.Lattice(c, storage=storage, layout="ab", init_fields=False, row0=i0)
+        i0 += n
         lat.set_fields(**f)
         slabs.append(lat)
     nb = slabs[0].halo_bytes()
