@@ -50,7 +50,11 @@ extern "C" {
                         rounding, 76 B per node update                         */
 #define AXLB_BF16 2  /* bfloat16, stochastic rounding, 76 B per node update    */
 /* Stochastic rounding draws its random bits from a hash of the value and
- * the slot, so that a run (and a checkpoint replay) is deterministic. */
+ * the slot, so that a run (and a checkpoint replay) is deterministic.
+ * bfloat16 with lagged derivatives stores each population minus its linear
+ * equilibrium part (3 w_q e_q.u for f, w_q u_theta for g, w_q (T - T_ref)
+ * for h) taken at the lagged fields of the node that wrote it; a checkpoint
+ * image of such a lattice loads only into another one. */
 
 /* ---- streaming layouts ---- */
 #define AXLB_LAYOUT_AA 0 /* one population buffer, in place, alternating phases */
