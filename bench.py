@@ -192,6 +192,39 @@ def cpu_leg(case, single_steps: int, multi_steps: int, gpu_accuracy):
     return base, accuracy
 
 
+def bench_small_members(n, steps, warmup):
+    """A batch of many small annuli (Nr ~ U{16..64}, Nz ~ U{16..128}, AA
+    members), stepped with every member on the work-list (autotuned tile and
+    schedule) and with each member whole in one workgroup (a bundle per
+    launch)."""
+    from paper_1806_10241_amd import axlb
+    from paper_1806_10241_amd import inputs as I
+
+    cases = I.batched_annuli(n=n, seed=7, nr=(16, 64), nz=(16, 128))
+    nodes = sum(c["Nr"] * c["Nz"] for c in cases)
+    lats = [axlb.Lattice(c) for c in cases]
+    b = axlb.Batch(lats)
+    tile, blocks, _ = b.autotune(steps_per_trial=20)
+    picked = b.whole()[0]
+    out = {"instances": n, "nodes": nodes, "steps": steps,
+           "work_list_schedule": {"tile": "%dx%d" % axlb.tile_shape(tile), "blocks": blocks},
+           "autotuner_picked_whole": picked > 0}
+    for name, limit in (("work_list", 0), ("whole_members", axlb.WHOLE_MAX_NODES)):
+        b.set_whole(limit)
+        b.step(warmup)
+        b.sync()
+        t0 = time.perf_counter()
+        b.step(steps)
+        b.sync()
+        dt = time.perf_counter() - t0
+        out[name] = {"mlups": round(nodes * steps / dt / 1e6, 1), "ms_per_step": round(dt / steps * 1e3, 4)}
+    b.close()
+    for lat in lats:
+        lat.close()
+    out["speedup_whole"] = round(out["whole_members"]["mlups"] / out["work_list"]["mlups"], 2)
+    return out
+
+
 def bench_batched(n, steps, warmup, baseline_steps):
     """256-way batch of uneven annulus-convection instances (seeded), two
     ways: single-buffer (AA) members in fused one-step launches with an
@@ -210,7 +243,8 @@ def bench_batched(n, steps, warmup, baseline_steps):
         sched = None
         if layout == "aa":
             tile, blocks, _ = b.autotune(steps_per_trial=20)
-            sched = {"tile": "%dx%d" % axlb.tile_shape(tile), "blocks": blocks}
+            sched = {"tile": "%dx%d" % axlb.tile_shape(tile), "blocks": blocks,
+                     "whole_members": b.whole()[1]}
         b.step(warmup)
         b.sync()
         t0 = time.perf_counter()
@@ -489,6 +523,8 @@ def main():
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10000)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--small-n", type=int, default=1024,
+                    help="members of the small-member batch")
     ap.add_argument("--serve-n", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-tol", type=float, default=1e-7)
@@ -603,6 +639,8 @@ def main():
     if not args.no_batch:
         print("bench: batched, %d instances" % args.batch_n, file=sys.stderr, flush=True)
         out["batched"] = bench_batched(args.batch_n, args.batch_steps, 200, args.batch_steps)
+        print("bench: batched, %d small instances" % args.small_n, file=sys.stderr, flush=True)
+        out["batched_small"] = bench_small_members(args.small_n, 2000, 200)
     if not args.no_serve:
         print("bench: served, %d requests" % args.serve_n, file=sys.stderr, flush=True)
         served = bench_served(args.serve_n, args.serve_rate, args.serve_tol,

@@ -366,10 +366,25 @@ int axlb_batch_sync(axlb_batch *b);
  * batch has one schedule). */
 int axlb_batch_set_schedule(axlb_batch *b, int tile, int blocks);
 int axlb_batch_get_schedule(const axlb_batch *b, int *tile, int *blocks);
+/* Whole members (AA members only): a member of at most max_nodes nodes
+ * (0 <= max_nodes <= AXLB_WHOLE_MAX_NODES; 0, the default, turns the mode
+ * off) runs in one workgroup of its own, which takes it through all the
+ * steps of a launch (a bundle's 100 in one kernel) with a workgroup barrier
+ * between steps; the other members keep the work-list.  During a bundle the
+ * whole members run on a chain of their own beside the work-list's.
+ * Results are bitwise those of the work-list.  AXLB_EINVAL for AB2 batches
+ * or max_nodes out of range.  axlb_batch_get_whole reports the limit and
+ * how many members run whole. */
+#define AXLB_WHOLE_MAX_NODES 65536
+int axlb_batch_set_whole(axlb_batch *b, long long max_nodes);
+int axlb_batch_get_whole(const axlb_batch *b, long long *max_nodes, int *members);
 /* Times every tile shape with each of the AXLB_NSCHEDULES schedules (one
  * workgroup per entry, 4, 8 and 16 persistent workgroups per compute unit)
  * for steps_per_trial steps (group by group, as the bundles of
- * axlb_batch_step run), restores the members' state, keeps the fastest.
+ * axlb_batch_step run); then, when some member has at most
+ * AXLB_WHOLE_MAX_NODES nodes, the best of them without and with whole
+ * members (each timed as a bundle runs); restores the members' state and
+ * keeps the fastest (axlb_batch_get_whole tells whether members run whole).
  * ms_per_step[AXLB_NTILES * AXLB_NSCHEDULES] may be NULL.  A batch of AB2
  * members has nothing to choose: it returns at once (times 0). */
 int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,

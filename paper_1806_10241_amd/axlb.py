@@ -37,6 +37,7 @@ EXPORTS = [
     "axlb_destroy", "axlb_last_error", "axlb_tile_shape", "axlb_set_tile", "axlb_get_tile",
     "axlb_autotune", "axlb_batch_create", "axlb_batch_size", "axlb_batch_step",
     "axlb_batch_sync", "axlb_batch_set_schedule", "axlb_batch_get_schedule",
+    "axlb_batch_set_whole", "axlb_batch_get_whole",
     "axlb_batch_autotune", "axlb_batch_destroy", "axlb_batch_last_error", "axlb_step_each",
     "axlb_halo_bytes", "axlb_halo_export", "axlb_halo_import",
     "axlb_pool_create", "axlb_pool_set_policy", "axlb_pool_submit", "axlb_pool_tick",
@@ -49,6 +50,7 @@ REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 POOL_ORDER = {"fifo": 0, "smallest": 1}
 NTILES = 8
 NSCHEDULES = 4
+WHOLE_MAX_NODES = 65536
 
 
 class AxlbError(RuntimeError):
@@ -134,6 +136,8 @@ def load():
         "axlb_batch_sync": ([_vp], C.c_int),
         "axlb_batch_set_schedule": ([_vp, C.c_int, C.c_int], C.c_int),
         "axlb_batch_get_schedule": ([_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+        "axlb_batch_set_whole": ([_vp, C.c_longlong], C.c_int),
+        "axlb_batch_get_whole": ([_vp, C.POINTER(C.c_longlong), C.POINTER(C.c_int)], C.c_int),
         "axlb_batch_autotune": ([_vp, C.c_int, _dp, C.POINTER(C.c_int), C.POINTER(C.c_int)],
                                 C.c_int),
         "axlb_batch_destroy": ([_vp], None),
@@ -434,13 +438,25 @@ class Batch:
         return t.value, b.value
 
     def autotune(self, steps_per_trial: int = 10):
-        """Times every (tile shape, schedule); keeps the fastest.  Returns
-        (tile, blocks, ms[tile][schedule])."""
+        """Times every (tile shape, schedule), then the best one with and
+        without whole members; keeps the fastest (``whole()`` tells whether
+        members run whole).  Returns (tile, blocks, ms[tile][schedule])."""
         ms = np.zeros(NTILES * NSCHEDULES)
         t, b = C.c_int(), C.c_int()
         self._check(self._lib.axlb_batch_autotune(self._h, int(steps_per_trial), _ptr(ms),
                                                   C.byref(t), C.byref(b)))
         return t.value, b.value, ms.reshape(NTILES, NSCHEDULES)
+
+    def set_whole(self, max_nodes: int):
+        """Members of at most max_nodes nodes (<= WHOLE_MAX_NODES) run one
+        per workgroup, a bundle per launch; 0 turns the mode off."""
+        self._check(self._lib.axlb_batch_set_whole(self._h, int(max_nodes)))
+
+    def whole(self):
+        """(max_nodes, members that run whole)."""
+        m, k = C.c_longlong(), C.c_int()
+        self._check(self._lib.axlb_batch_get_whole(self._h, C.byref(m), C.byref(k)))
+        return m.value, k.value
 
 
 def make_request(case: dict, storage: str = "f32", tol: float = 1e-7,

@@ -108,6 +108,70 @@ static hipError_t launch_batch(int storage, int tile, int blocks, const InstDesc
     return launch_batch_t<float>(tile, blocks, D, tiles, t0, ntiles, phase, st);
 }
 
+// Whole members: members of at most WHOLE_MAX_NODES nodes may instead run
+// one per workgroup, which takes the member through `nsteps` steps in one
+// launch (a bundle's 100 steps in one kernel) with a workgroup barrier
+// between steps: no launch per step, and the member's edge nodes run in the
+// same workgroup as its interior.  Every node of an AA phase reads and
+// writes only its own 19 slots, so the threads of a step need no order
+// among themselves; the barrier (with its workgroup-scope fences) makes a
+// step's stores visible to the next step's loads.  Thread k of the
+// workgroup takes nodes k, k + WHOLE_THREADS, ... in row-major order.
+constexpr int WHOLE_THREADS = 1024;
+constexpr long long WHOLE_MAX_NODES = AXLB_WHOLE_MAX_NODES;
+
+template <class S>
+__global__ void __launch_bounds__(WHOLE_THREADS)
+    k_batch_whole(const InstDesc *__restrict__ D, const int *__restrict__ whole, int nwhole,
+                  int phase0, int nsteps) {
+    const int tid = (int)threadIdx.x;
+    for (int w = (int)blockIdx.x; w < nwhole; w += (int)gridDim.x) {
+        const InstDesc *d = D + whole[w];
+        S *A = (S *)d->pop;
+        const int Nr = d->P.Nr, N = Nr * d->P.Nz, ne = edge_count(Nr, d->P.Nz);
+        const int di = WHOLE_THREADS / Nr, dj = WHOLE_THREADS % Nr;
+        const int i0 = tid / Nr, j0 = tid % Nr;
+        for (int s = 0; s < nsteps; ++s) {
+            const bool odd = (d->parity0 ^ ((phase0 + s) & 1)) == 0;
+            if (odd) {
+                for (int e = tid; e < ne; e += WHOLE_THREADS) {
+                    int i, j;
+                    edge_node(d->P, e, i, j);
+                    update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j, false);
+                }
+            }
+            int i = i0, j = j0;
+            for (int k = tid; k < N; k += WHOLE_THREADS) {
+                if (odd) {
+                    if (interior_node(d->P, i, j)) update_planes<S>(d->P, d->pl[1], i, j, true);
+                } else {
+                    update_planes<S>(d->P, d->pl[0], i, j, interior_node(d->P, i, j));
+                }
+                i += di;
+                j += dj;
+                if (j >= Nr) {
+                    j -= Nr;
+                    ++i;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+static hipError_t launch_whole(int storage, const InstDesc *D, const int *whole, int nwhole,
+                               int phase0, int nsteps, hipStream_t st) {
+    if (nwhole == 0) return hipSuccess;
+    const dim3 grid(nwhole), block(WHOLE_THREADS);
+    if (storage == STORE_F16)
+        k_batch_whole<__half><<<grid, block, 0, st>>>(D, whole, nwhole, phase0, nsteps);
+    else if (storage == STORE_BF16)
+        k_batch_whole<__hip_bfloat16><<<grid, block, 0, st>>>(D, whole, nwhole, phase0, nsteps);
+    else
+        k_batch_whole<float><<<grid, block, 0, st>>>(D, whole, nwhole, phase0, nsteps);
+    return hipGetLastError();
+}
+
 }  // namespace axlb
 
 using namespace axlb;
@@ -120,6 +184,14 @@ struct axlb_batch {
     // device and one group's launch ramp and tail overlap the other's work
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    // whole members (AA): those of at most whole_max nodes run one per
+    // workgroup (d_whole lists them, nwhole of them), on the chain `aux`
+    // during a bundle; the work-list holds the others
+    long long whole_max = 0;
+    int *d_whole = nullptr;
+    int nwhole = 0;
+    hipStream_t aux = nullptr;
+    hipEvent_t join_aux = nullptr;
     std::vector<axlb_lattice *> members;
     std::vector<hipStream_t> member_streams;
     int storage = 0;
@@ -229,7 +301,7 @@ static int build_worklist(axlb_batch *b) {
     int bx, by;
     tile_shape(b->tile, &bx, &by);
     std::vector<InstDesc> desc(b->members.size());
-    std::vector<int> tiles;
+    std::vector<int> tiles, whole;
     b->group.clear();
     size_t group_bytes = 0;
     for (size_t m = 0; m < b->members.size(); ++m) {
@@ -243,31 +315,46 @@ static int build_worklist(axlb_batch *b) {
         d.pl[0] = step_planes(L->P, L->storage, MODE_AA_EVEN, d.pop, d.pop, d.lag[1], d.lag[0]);
         d.pl[1] = step_planes(L->P, L->storage, MODE_AA_ODD, d.pop, d.pop, d.lag[0], d.lag[1]);
         d.parity0 = (int)((L->steps - b->steps) & 1);
+        if ((long long)L->Nr * L->Nz <= b->whole_max) {  // one workgroup takes it whole
+            whole.push_back((int)m);
+            continue;
+        }
         d.gx = (L->Nr + bx - 1) / bx;
         const int gy = (L->Nz + by - 1) / by;
         d.nedge = (edge_count(L->Nr, L->Nz) + bx * by - 1) / (bx * by);
         d.tile_begin = (int)tiles.size();
         tiles.insert(tiles.end(), (size_t)d.nedge + (size_t)d.gx * gy, (int)m);
         const size_t bytes = L->lay.pop_bytes + 2 * L->lay.lag_bytes;
-        if (m == 0 || group_bytes + bytes > GROUP_BYTES) {
+        if (b->group.empty() || group_bytes + bytes > GROUP_BYTES) {
             b->group.push_back(d.tile_begin);
             group_bytes = 0;
         }
         group_bytes += bytes;
     }
+    if (b->group.empty()) b->group.push_back(0);
     b->group.push_back((int)tiles.size());
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_whole) (void)hipFree(b->d_whole);
     b->d_desc = nullptr;
     b->d_tiles = nullptr;
+    b->d_whole = nullptr;
+    b->ntiles = 0;
+    b->nwhole = 0;
     BHIP(b, hipMalloc((void **)&b->d_desc, desc.size() * sizeof(InstDesc)));
-    BHIP(b, hipMalloc((void **)&b->d_tiles, tiles.size() * sizeof(int)));
+    BHIP(b, hipMalloc((void **)&b->d_tiles, (tiles.size() + 1) * sizeof(int)));
+    BHIP(b, hipMalloc((void **)&b->d_whole, (whole.size() + 1) * sizeof(int)));
     BHIP(b, hipMemcpyAsync(b->d_desc, desc.data(), desc.size() * sizeof(InstDesc),
                            hipMemcpyHostToDevice, b->stream));
-    BHIP(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(int),
-                           hipMemcpyHostToDevice, b->stream));
+    if (!tiles.empty())
+        BHIP(b, hipMemcpyAsync(b->d_tiles, tiles.data(), tiles.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
+    if (!whole.empty())
+        BHIP(b, hipMemcpyAsync(b->d_whole, whole.data(), whole.size() * sizeof(int),
+                               hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     b->ntiles = (int)tiles.size();
+    b->nwhole = (int)whole.size();
     drop_batch_graphs(b);
     return AXLB_OK;
 }
@@ -275,6 +362,7 @@ static int build_worklist(axlb_batch *b) {
 // One step (parity s & 1) of the work-list entries [t0, t1).
 static int batch_launch(axlb_batch *b, long s, int t0, int t1, hipStream_t st) {
     const int n = t1 - t0;
+    if (n <= 0) return AXLB_OK;  // every member runs whole
     int blocks = b->blocks > 0 ? b->blocks : n;
     if (blocks < 8) blocks = 8;  // every XCD chunk needs a block
     hipError_t e = launch_batch(b->storage, b->tile, blocks, b->d_desc, b->d_tiles, t0, n,
@@ -287,6 +375,35 @@ static int batch_launch(axlb_batch *b, long s, int t0, int t1) {
     return batch_launch(b, s, t0, t1, b->stream);
 }
 static int batch_launch(axlb_batch *b, long s) { return batch_launch(b, s, 0, b->ntiles); }
+
+// `nsteps` steps of the whole members from batch step s, on stream st.
+static int whole_launch(axlb_batch *b, long s, int nsteps, hipStream_t st) {
+    const hipError_t e = launch_whole(b->storage, b->d_desc, b->d_whole, b->nwhole, (int)(s & 1),
+                                      nsteps, st);
+    if (e != hipSuccess) return bfail(b, AXLB_EDEVICE, std::string("whole-member launch: ") + hipGetErrorString(e));
+    return AXLB_OK;
+}
+
+// Steps s .. s + nsteps - 1 of an AA batch as a bundle runs them: the
+// whole members in one launch on the chain `aux`, the work-list group by
+// group on the two chains `stream` and `side`, joined back into `stream`.
+static int bundle_launches(axlb_batch *b, long s, int nsteps) {
+    int rc = AXLB_OK;
+    hipError_t fe = hipEventRecord(b->fork, b->stream);
+    if (fe == hipSuccess) fe = hipStreamWaitEvent(b->side, b->fork, 0);
+    if (fe == hipSuccess) fe = hipStreamWaitEvent(b->aux, b->fork, 0);
+    if (fe != hipSuccess) return bfail(b, AXLB_EDEVICE, "batch fork failed");
+    if (b->nwhole > 0) rc = whole_launch(b, s, nsteps, b->aux);
+    for (size_t g = 0; g + 1 < b->group.size() && rc == AXLB_OK; ++g)
+        for (long k = 0; k < nsteps && rc == AXLB_OK; ++k)
+            rc = batch_launch(b, s + k, b->group[g], b->group[g + 1], g % 2 ? b->side : b->stream);
+    fe = hipEventRecord(b->join, b->side);
+    if (fe == hipSuccess) fe = hipStreamWaitEvent(b->stream, b->join, 0);
+    if (fe == hipSuccess) fe = hipEventRecord(b->join_aux, b->aux);
+    if (fe == hipSuccess) fe = hipStreamWaitEvent(b->stream, b->join_aux, 0);
+    if (fe != hipSuccess && rc == AXLB_OK) rc = bfail(b, AXLB_EDEVICE, "batch join failed");
+    return rc;
+}
 
 static void advance_members(axlb_batch *b, long n) {
     b->steps += n;
@@ -398,10 +515,14 @@ int axlb_batch_create(axlb_lattice *const *lats, int n, axlb_batch **out) {
     if (hipSetDevice(dev) != hipSuccess ||
         hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join_aux, hipEventDisableTiming) != hipSuccess) {
+        if (b->join_aux) (void)hipEventDestroy(b->join_aux);
         if (b->join) (void)hipEventDestroy(b->join);
         if (b->fork) (void)hipEventDestroy(b->fork);
+        if (b->aux) (void)hipStreamDestroy(b->aux);
         if (b->side) (void)hipStreamDestroy(b->side);
         if (b->stream) (void)hipStreamDestroy(b->stream);
         delete b;
@@ -462,6 +583,25 @@ int axlb_batch_get_schedule(const axlb_batch *b, int *tile, int *blocks) {
     return AXLB_OK;
 }
 
+int axlb_batch_set_whole(axlb_batch *b, long long max_nodes) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    if (max_nodes < 0 || max_nodes > WHOLE_MAX_NODES)
+        return bfail(b, AXLB_EINVAL, "max_nodes must lie in [0, AXLB_WHOLE_MAX_NODES]");
+    if (b->layout == AXLB_LAYOUT_AB2)
+        return bfail(b, AXLB_EINVAL, "whole members are for AA members");
+    BHIP(b, hipSetDevice(b->device));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    b->whole_max = max_nodes;
+    return build_worklist(b);
+}
+
+int axlb_batch_get_whole(const axlb_batch *b, long long *max_nodes, int *members) {
+    if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
+    if (max_nodes) *max_nodes = b->whole_max;
+    if (members) *members = b->nwhole;
+    return AXLB_OK;
+}
+
 int axlb_batch_step(axlb_batch *b, long n) {
     if (!b) return bfail(nullptr, AXLB_EINVAL, "batch is NULL");
     if (n < 0) return bfail(b, AXLB_EINVAL, "negative step count");
@@ -474,18 +614,9 @@ int axlb_batch_step(axlb_batch *b, long n) {
                 BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
                 // group by group, alternate groups on two chains: each
                 // group's state stays in the Infinity Cache for the whole
-                // bundle, and two groups run side by side
-                int rc = AXLB_OK;
-                hipError_t fe = hipEventRecord(b->fork, b->stream);
-                if (fe == hipSuccess) fe = hipStreamWaitEvent(b->side, b->fork, 0);
-                if (fe != hipSuccess) rc = bfail(b, AXLB_EDEVICE, "batch graph fork failed");
-                for (size_t g = 0; g + 1 < b->group.size() && rc == AXLB_OK; ++g)
-                    for (long s = 0; s < BUNDLE && rc == AXLB_OK; ++s)
-                        rc = batch_launch(b, k + s, b->group[g], b->group[g + 1],
-                                          g % 2 ? b->side : b->stream);
-                fe = hipEventRecord(b->join, b->side);
-                if (fe == hipSuccess) fe = hipStreamWaitEvent(b->stream, b->join, 0);
-                if (fe != hipSuccess && rc == AXLB_OK) rc = bfail(b, AXLB_EDEVICE, "batch graph join failed");
+                // bundle, and two groups run side by side; the whole
+                // members take the bundle in one launch on a third chain
+                const int rc = bundle_launches(b, k, (int)BUNDLE);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(b->stream, &g);
                 if (rc != AXLB_OK) {
@@ -504,7 +635,8 @@ int axlb_batch_step(axlb_batch *b, long n) {
             advance_members(b, BUNDLE);
             n -= BUNDLE;
         } else {
-            int rc = batch_launch(b, b->steps);
+            int rc = whole_launch(b, b->steps, 1, b->stream);
+            if (rc == AXLB_OK) rc = batch_launch(b, b->steps);
             if (rc) return rc;
             advance_members(b, 1);
             n -= 1;
@@ -555,8 +687,12 @@ int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
     BHIP(b, hipEventCreate(&e0));
     BHIP(b, hipEventCreate(&e1));
     const long steps0 = b->steps;
+    const int tile0 = b->tile, blocks0 = b->blocks;
+    const long long whole0 = b->whole_max;
     double best_ms = 1e300;
     int bt = b->tile, bb = b->blocks, rc = AXLB_OK;
+    long long bw = 0;
+    b->whole_max = 0;  // the work-list schedules first, every member in the list
     for (int t = 0; t < tile_count() && rc == AXLB_OK; ++t) {
         b->tile = t;
         rc = build_worklist(b);
@@ -583,6 +719,32 @@ int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
             }
         }
     }
+    // then the best schedule without and with whole members, each timed as
+    // a bundle runs (the chains side by side)
+    bool any_small = false;
+    for (const axlb_lattice *L : b->members)
+        any_small = any_small || (long long)L->Nr * L->Nz <= WHOLE_MAX_NODES;
+    if (any_small && rc == AXLB_OK) {
+        b->tile = bt;
+        b->blocks = bb;
+        double per_mode[2] = {0.0, 0.0};
+        for (int mode = 0; mode < 2 && rc == AXLB_OK; ++mode) {
+            b->whole_max = mode ? WHOLE_MAX_NODES : 0;
+            rc = build_worklist(b);
+            if (rc == AXLB_OK) rc = bundle_launches(b, b->steps, 2);
+            b->steps += 2;
+            (void)hipEventRecord(e0, b->stream);
+            if (rc == AXLB_OK) rc = bundle_launches(b, b->steps, steps_per_trial);
+            b->steps += steps_per_trial;
+            (void)hipEventRecord(e1, b->stream);
+            float ms = 0.f;
+            if (rc == AXLB_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = bfail(b, AXLB_EDEVICE, "autotune timing");
+            per_mode[mode] = ms / steps_per_trial;
+        }
+        if (rc == AXLB_OK && per_mode[1] < per_mode[0]) bw = WHOLE_MAX_NODES;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     // restore every member and the batch step count
@@ -594,9 +756,16 @@ int axlb_batch_autotune(axlb_batch *b, int steps_per_trial, double *ms_per_step,
     (void)hipStreamSynchronize(b->stream);
     release();
     b->steps = steps0;
-    if (rc != AXLB_OK) return rc;
+    if (rc != AXLB_OK) {  // keep the schedule the batch had
+        b->tile = tile0;
+        b->blocks = blocks0;
+        b->whole_max = whole0;
+        (void)build_worklist(b);
+        return rc;
+    }
     b->tile = bt;
     b->blocks = bb;
+    b->whole_max = bw;
     rc = build_worklist(b);
     if (rc != AXLB_OK) return rc;
     if (best_tile) *best_tile = bt;
@@ -617,8 +786,11 @@ void axlb_batch_destroy(axlb_batch *b) {
     if (b->d_two) (void)hipFree(b->d_two);
     if (b->d_two_tiles) (void)hipFree(b->d_two_tiles);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
+    if (b->d_whole) (void)hipFree(b->d_whole);
+    if (b->join_aux) (void)hipEventDestroy(b->join_aux);
     if (b->join) (void)hipEventDestroy(b->join);
     if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->aux) (void)hipStreamDestroy(b->aux);
     if (b->side) (void)hipStreamDestroy(b->side);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     delete b;

@@ -90,6 +90,12 @@ __device__ __forceinline__ float lag_round(int v, float x) {
 // Everything a step kernel needs, passed by value.
 struct KParams {
     int Nr, Nz, pitch;     // fluid nodes along r, z; row pitch (elements)
+    // Global index of row 0 (a slab of a taller lattice): the stochastic
+    // rounding of 16-bit stores keys on global rows.  It sits in the
+    // alignment gap before `plane`: a larger parameter block made the step
+    // kernels spill scalar registers (about 6400 v_readlane in the FP32
+    // two-step kernel against 700).
+    int row0;
     long long plane;       // elements per population / field plane
     float r0;              // radius of node row j is r0 + j + 1/2
     float nu, alpha;
@@ -113,9 +119,6 @@ struct KParams {
     // planes (lag_ld layout)
     const void *halo_pop[2];
     const char *halo_lag[2];
-    // Global index of row 0 (a slab of a taller lattice): the stochastic
-    // rounding of 16-bit stores keys on global rows.
-    int row0;
 };
 
 // Plane addresses of one step launch, for the tile workgroups of the step

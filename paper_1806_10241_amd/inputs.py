@@ -321,15 +321,16 @@ def czochralski_melt(N: int = 40, Re_x: float = 100.0, Re_c: float = -25.0, Pr: 
                 outer=outer, T_ref=0.5, seed=seed, fields=_perturbed_T(seed, Nz, N))
 
 
-def batched_annuli(n: int = 256, seed: int = 4):
-    """Uneven annulus convection instances: Nr ~ U{48..256}, Nz ~ U{48..512},
-    Ra log-uniform in [1e3, 1e6], Pr log-uniform in [0.02, 7], radius ratio
-    uniform in [1.5, 4]; instance k uses seed*1000 + k for its noise."""
+def batched_annuli(n: int = 256, seed: int = 4, nr=(48, 256), nz=(48, 512)):
+    """Uneven annulus convection instances: Nr ~ U{48..256}, Nz ~ U{48..512}
+    (or the given ranges), Ra log-uniform in [1e3, 1e6], Pr log-uniform in
+    [0.02, 7], radius ratio uniform in [1.5, 4]; instance k uses
+    seed*1000 + k for its noise."""
     u = uniform(seed, 5 * n).reshape(n, 5)
     cases = []
     for k in range(n):
-        Nr = 48 + int(u[k, 0] * (256 - 48 + 1))
-        Nz = 48 + int(u[k, 1] * (512 - 48 + 1))
+        Nr = nr[0] + int(u[k, 0] * (nr[1] - nr[0] + 1))
+        Nz = nz[0] + int(u[k, 1] * (nz[1] - nz[0] + 1))
         Ra = 10.0 ** (3.0 + 3.0 * u[k, 2])
         Pr = 10.0 ** (math.log10(0.02) + (math.log10(7.0) - math.log10(0.02)) * u[k, 3])
         ratio = 1.5 + 2.5 * u[k, 4]

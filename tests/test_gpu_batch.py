@@ -43,6 +43,44 @@ def test_batch_equals_alone(gpu, storage):
     b.close()
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_whole_members_equal_alone(gpu, storage):
+    """Members of at most WHOLE_MAX_NODES nodes run one per workgroup, a
+    bundle per launch with a workgroup barrier per step, beside a member too
+    large for the mode on the work-list: after bundles, single steps and an
+    odd count every member equals stepping alone bit for bit, also when the
+    mode is switched mid-run, and a member joins with the other phase."""
+    say("whole members", storage)
+    from paper_1806_10241_amd import axlb
+    cases = members()
+    cases.append(I.annulus_convection(Nr=300, Nz=260, Ra=1e4, seed=49))  # 78000 nodes
+    cases.append(I.couette_poiseuille_conduction(Nr=2, Nz=3))
+    alone = [axlb.Lattice(c, storage=storage) for c in cases]
+    batched = [axlb.Lattice(c, storage=storage) for c in cases]
+    alone[2].step(1)
+    batched[2].step(1)
+    b = axlb.Batch(batched)
+    b.set_whole(axlb.WHOLE_MAX_NODES)
+    small = sum(c["Nr"] * c["Nz"] <= axlb.WHOLE_MAX_NODES for c in cases)
+    assert b.whole() == (axlb.WHOLE_MAX_NODES, small) and small == len(cases) - 1
+    b.step(237)
+    b.set_whole(0)
+    assert b.whole() == (0, 0)
+    b.step(3)
+    b.set_whole(5000)
+    b.step(101)
+    b.sync()
+    for lat in alone:
+        lat.step(341)
+    for la, lb in zip(alone, batched):
+        assert lb.steps == la.steps
+        assert la.save() == lb.save()
+    lib = axlb.load()
+    assert lib.axlb_batch_set_whole(b._h, axlb.WHOLE_MAX_NODES + 1) == axlb.EINVAL
+    assert lib.axlb_batch_set_whole(b._h, -1) == axlb.EINVAL
+    b.close()
+
+
 def test_cache_groups_on_two_streams_equal_alone(gpu):
     """Members whose states exceed one cache group: a bundle splits them into
     groups that alternate between two streams; every member still ends
