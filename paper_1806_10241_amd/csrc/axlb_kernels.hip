@@ -30,13 +30,23 @@ namespace axlb {
 // compute units (the other wavefronts of an edge workgroup exit at once).
 constexpr int EDGE_PER_BLOCK = 64;
 
+// Whether a step of slot convention `mode` runs the lattice's edge nodes in
+// workgroups of their own.
+template <class S>
+__host__ __device__ constexpr bool split_edges(int mode) {
+    return mode != MODE_AA_EVEN || kEnc<S>;
+}
+
 // One time step for every node of one lattice.  Where boundary rules apply
 // to the streaming (AA odd phase, AB), the first workgroups take
 // EDGE_PER_BLOCK consecutive edge nodes each (their count rounded up to a
 // multiple of 8, so that the hardware deals them to all eight XCDs and the
 // tiles after them keep their XCD alignment), and the tile workgroups skip
 // the edge nodes; the AA even phase streams within each node's own slots, so its
-// tiles take every node.  Tile workgroups are XCD-remapped as in tile_of
+// tiles take every node, except with offset-encoded bfloat16, whose even phase
+// finds the writer of an edge node's slots through the boundary rules (that
+// code in every tile workgroup cost 10 us of 51 per even step at 1024 x 2048).
+// Tile workgroups are XCD-remapped as in tile_of
 // and reach every value through the launch's plane addresses (Planes); edge
 // workgroups take the general per-node path.
 template <class S, int MODE, int BX, int BY>
@@ -44,7 +54,7 @@ __global__ void __launch_bounds__(BX * BY) k_step(const KParams P, const Planes 
                                                    const S *src, S *dst,
                                                    const char *__restrict__ Mprev,
                                                    char *__restrict__ Mnext) {
-    constexpr bool SPLIT = MODE != MODE_AA_EVEN;
+    constexpr bool SPLIT = split_edges<S>(MODE);
     const int gx = (P.Nr + BX - 1) / BX;
     const int ne = SPLIT ? edge_blocks(P.Nr, P.Nz, EDGE_PER_BLOCK) : 0;
     const int b = (int)blockIdx.x;
@@ -328,7 +338,7 @@ Planes step_planes(const KParams &P, int storage, int mode, const void *src, voi
 template <class S, int BX, int BY>
 static void launch_step_tile(const KParams &P, int mode, S *a, S *b, const char *Mprev,
                              char *Mnext, hipStream_t st) {
-    const int edges = mode == MODE_AA_EVEN ? 0 : edge_blocks(P.Nr, P.Nz, EDGE_PER_BLOCK);
+    const int edges = split_edges<S>(mode) ? edge_blocks(P.Nr, P.Nz, EDGE_PER_BLOCK) : 0;
     const dim3 grid(grid_for(P, BX, BY).x + edges), block(BX * BY);
     const Planes A = step_planes(P, store_of<S>(), mode, a, mode == MODE_AB ? b : a, Mprev, Mnext);
     switch (mode) {
