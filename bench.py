@@ -484,6 +484,46 @@ def out_of_cache(Nr, Nz, steps, storage="f32"):
     return out
 
 
+def storage_variants(Nr, Nz, steps):
+    """The headline workload with 16-bit population storage (binary16, and
+    bfloat16 stored relative to its writer's linear equilibrium; FP32
+    arithmetic), single-buffer (AA) and two steps per launch (AB2): graph
+    replays timed with HIP events on the lattice's stream.  Their accuracy
+    against the oracle is in `accuracy`."""
+    import torch
+
+    from paper_1806_10241_amd import axlb
+    from paper_1806_10241_amd import inputs as I
+    case = I.rotating_lid_cylinder(Nr=Nr, Nz=Nz, Re=1000.0, Ri=0.5, u_noise=1e-4)
+    nodes = Nr * Nz
+    out = {"Nr": Nr, "Nz": Nz, "steps": steps, "bytes_per_node_update": 76}
+    for storage in ("f16", "bf16"):
+        out[storage] = {}
+        for layout in ("aa", "ab2"):
+            stream = torch.cuda.Stream()
+            lat = axlb.Lattice(case, storage=storage, layout=layout, stream=stream)
+            if layout == "aa":
+                lat.set_tile(axlb_default_tile())
+            lat.step(20)
+            lat.prepare_steps(steps)
+            lat.sync()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lat.step(steps)
+            b.record(stream)
+            b.synchronize()
+            ms = a.elapsed_time(b) / steps
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+            achieved = BYTES_PER_UPDATE[storage] * nodes / (ms / 1e3) / 1e9
+            out[storage][layout] = {"mlups": round(nodes / (ms / 1e3) / 1e6, 1),
+                                    "ms_per_step": round(ms, 4),
+                                    "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    return out
+
+
 def axlb_default_tile():
     """The 256 x 1 tile (the autotuner's usual choice at these widths)."""
     from paper_1806_10241_amd import axlb
@@ -516,6 +556,8 @@ def main():
                     help="step-kernel tile shape; -1: autotune on the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the 16-bit storage step rates")
     ap.add_argument("--ooc-Nr", type=int, default=2048,
                     help="width of the out-of-cache lattice (0: skip that measurement)")
     ap.add_argument("--ooc-Nz", type=int, default=4096)
@@ -632,6 +674,9 @@ def main():
         print("bench: out-of-cache %dx%d" % (args.ooc_Nr, args.ooc_Nz), file=sys.stderr,
               flush=True)
         out["out_of_cache"] = out_of_cache(args.ooc_Nr, args.ooc_Nz, args.ooc_steps, args.storage)
+    if args.storage == "f32" and not args.no_variants:
+        print("bench: 16-bit storage variants", file=sys.stderr, flush=True)
+        out["storage_variants"] = storage_variants(args.Nr, args.Nz, 1000)
     gpu_accuracy = None
     if not args.no_accuracy:
         print("bench: accuracy runs", file=sys.stderr, flush=True)
