@@ -316,22 +316,36 @@ def test_full_size_parity_in_bench_configuration(gpu, orc):
         assert np.linalg.norm(dg - dr) <= 1e-3 * np.linalg.norm(dr), k
 
 
-def test_full_size_parity_over_a_graph_bundle(gpu, orc):
-    """The benchmark workload at 1024 x 2048 from its own seeded initial
-    state, 100 steps (one captured graph bundle, autotuned tile) against the
-    oracle on every node."""
-    say("full size 1024x2048, 100 steps")
-    from paper_1806_10241_amd import axlb
-    c = I.rotating_lid_cylinder(Nr=1024, Nz=2048, Re=1000.0, Ri=0.5, u_noise=1e-4)
-    lat = axlb.Lattice(c)
-    lat.autotune(steps_per_trial=4)
-    lat.step(100)
+def bench_case():
+    return I.rotating_lid_cylinder(Nr=1024, Nz=2048, Re=1000.0, Ri=0.5, u_noise=1e-4)
+
+
+@pytest.fixture(scope="module")
+def bench_oracle_100(orc):
+    """The oracle's fields after 100 steps of the benchmark workload."""
+    c = bench_case()
     ref = orc.Lattice(c, deriv_mode=orc.DERIV_PREVIOUS, fields=c["fields"]())
     ref.step(100)
-    F, R = lat.fields(), ref.fields()
+    return ref.fields()
+
+
+@pytest.mark.parametrize("storage,layout", [("f32", "aa"), ("f32", "ab2"), ("f16", "aa"),
+                                            ("bf16", "aa"), ("bf16", "ab2")])
+def test_full_size_parity_over_a_graph_bundle(gpu, bench_oracle_100, storage, layout):
+    """The benchmark workload at 1024 x 2048 from its own seeded initial
+    state, 100 steps (one captured graph bundle; the autotuned tile for AA)
+    against the oracle on every node, in each storage and layout the bench
+    line reports."""
+    say("full size 1024x2048, 100 steps", storage, layout)
+    from paper_1806_10241_amd import axlb
+    lat = axlb.Lattice(bench_case(), storage=storage, layout=layout)
+    if layout == "aa":
+        lat.autotune(steps_per_trial=4)
+    lat.step(100)
+    F, R = lat.fields(), bench_oracle_100
     say("  errors", {k: "%.2e" % v[0] for k, v in field_errors(F, R).items()},
         "max", {k: "%.2e" % v for k, v in max_errors(F, R).items()})
-    assert_parity(F, R, TOL["f32"], "t=100", TOL_DRHO["f32"])
+    assert_parity(F, R, TOL[storage], ("t=100", storage, layout), TOL_DRHO[storage])
 
 
 @pytest.mark.parametrize("kind", ["annulus", "lid"])
