@@ -1,13 +1,16 @@
 """Throughput of the axisymmetric cascaded LB time step on one MI355X.
 
 Workload: the 1024 x 2048 rotating-lid cylinder with buoyancy (Re = 1000,
-Ri = 0.5, Pr = 1), FP32 arithmetic and storage, single-buffer (AA) layout,
-steps replayed as captured HIP graphs.  A step is one update of every node's
-19 populations (D2Q9 + 2 x D2Q5).  Prints one JSON line.
+Ri = 0.5, Pr = 1), FP32 arithmetic and storage, in the faster (by a short
+trial) of the single-buffer layout (AA, one step per launch) and the
+two-buffer layout with two steps per launch (AB2), steps replayed as
+captured HIP graphs.  A step is one update of every node's 19 populations
+(D2Q9 + 2 x D2Q5).  Prints one JSON line.
 
-The dominant (only) kernel per step is the fused step kernel; its
-algorithmic traffic is 152 B per node update (19 populations x 4 B, read and
-written once), so achieved GB/s = 152 * nodes / average step time.  Beside
+The dominant (only) kernel is the fused step kernel (k_step, or k_step_two
+for two steps); its algorithmic traffic is 152 B per node update (19
+populations x 4 B, read and written once), so achieved GB/s = 152 * nodes /
+average step time.  Beside
 the headline the line carries: the same step on a lattice too large for the
 Infinity Cache, the error of every storage type against the FP64 oracle,
 the batched and served workloads, and the oracle's own speed on the host.
@@ -337,11 +340,12 @@ def bench_served(n, rate, tol, max_steps, budget_gib, max_nr_log2, max_nz_log2, 
            "aggregate_mlups": round(node_updates / makespan / 1e6, 1)}
     if not baseline:
         return out
-    # one request at a time: each case alone, same stop rule, FIFO queue
+    # one request at a time: each case alone in the pool's layout for its
+    # storage, same stop rule, FIFO queue
     finish = 0.0
     lat1 = []
     for at, case, st in trace:
-        lat = axlb.Lattice(case, storage=st)
+        lat = axlb.Lattice(case, storage=st, layout="ab2" if st == "f32" else "aa")
         t1 = time.perf_counter()
         lat.residual()
         while lat.steps < max_steps:

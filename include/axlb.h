@@ -406,8 +406,11 @@ int axlb_step_each(axlb_lattice *const *lats, int n, long steps);
  * batch per storage type, overlapping on the device), then retires every
  * request whose residual (axlb_residual, checked once per bundle) is below
  * its tol or whose step count reached max_steps.  Requests submitted
- * between ticks join at the next tick.  A request's result is bit-identical
- * to running the same case alone for the same number of steps. */
+ * between ticks join at the next tick.  FP32 requests run in the two-step
+ * layout (AXLB_LAYOUT_AB2), 16-bit ones in the single-buffer layout
+ * (AXLB_LAYOUT_AA); the budget counts axlb_state_bytes of that layout.  A
+ * request's result is bit-identical to running the same case alone in that
+ * layout for the same number of steps. */
 typedef struct axlb_pool axlb_pool;
 #define AXLB_REQ_QUEUED 0
 #define AXLB_REQ_RUNNING 1

@@ -59,12 +59,21 @@ static int pfail(axlb_pool *p, int code, const std::string &m) {
     return code;
 }
 
+// Layout of a request's lattice: FP32 requests take two steps per launch on
+// two buffers (AXLB_LAYOUT_AB2, the faster batch in FP32: 26.9k against
+// 23.5k MLUPS over 256 uneven annuli); 16-bit requests keep the single
+// buffer, whose step is faster than the two-step one with 16-bit storage
+// (binary16 at 1024 x 2048: 40.6 us against 45.8 us per step).
+static int pool_layout(int storage) {
+    return storage == AXLB_F32 ? AXLB_LAYOUT_AB2 : AXLB_LAYOUT_AA;
+}
+
 static int make_lattice(Req &q, int device) {
     const axlb_request &r = q.r;
     axlb_options o;
     std::memset(&o, 0, sizeof(o));
     o.storage = r.storage;
-    o.layout = AXLB_LAYOUT_AA;
+    o.layout = pool_layout(r.storage);
     o.T_ref = r.T_ref;
     o.device = device;
     axlb_lattice *L = nullptr;
@@ -158,7 +167,7 @@ int axlb_pool_set_policy(axlb_pool *p, int order, long long node_window) {
 int axlb_pool_submit(axlb_pool *p, const axlb_request *r, long *id) {
     if (!p || !r || !id) return pfail(p, AXLB_EINVAL, "NULL argument");
     size_t bytes = 0;
-    int rc = axlb_state_bytes(r->Nr, r->Nz, r->storage, AXLB_LAYOUT_AA, &bytes);
+    int rc = axlb_state_bytes(r->Nr, r->Nz, r->storage, pool_layout(r->storage), &bytes);
     if (rc != AXLB_OK) return pfail(p, rc, axlb_last_error(nullptr));
     if (bytes > p->budget) return pfail(p, AXLB_ENOMEM, "request larger than the pool budget");
     if (!(r->tol >= 0.0) || r->max_steps <= 0) return pfail(p, AXLB_EINVAL, "bad stop rule");

@@ -19,11 +19,16 @@ def requests():
     ]
 
 
+def pool_layout(storage):
+    """The layout the pool gives a request of this storage."""
+    return "ab2" if storage == "f32" else "aa"
+
+
 def test_pool_results_equal_alone(gpu):
     say("pool vs alone")
     from paper_1806_10241_amd import axlb
     reqs = requests()
-    sizes = [axlb.state_bytes(c["Nr"], c["Nz"], st) for c, st in reqs]
+    sizes = [axlb.state_bytes(c["Nr"], c["Nz"], st, pool_layout(st)) for c, st in reqs]
     pool = axlb.Pool(budget_bytes=sizes[0] + sizes[1] + sizes[2])
     ids = [pool.submit(c, st, tol=0.0, max_steps=300) for c, st in reqs[:2]]
     assert pool.tick() == (2, 0)
@@ -39,7 +44,7 @@ def test_pool_results_equal_alone(gpu):
         state, steps, _ = pool.status(rid)
         assert state == axlb.REQ_DONE and steps == 300
         got, nu = pool.result(rid)
-        lat = axlb.Lattice(c, storage=st)
+        lat = axlb.Lattice(c, storage=st, layout=pool_layout(st))
         lat.step(300)
         ref = lat.fields()
         for k in ref:
