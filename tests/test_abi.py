@@ -75,3 +75,21 @@ def test_current_derivatives_rejected_with_one_buffer():
         rc = lib.axlb_lattice_create(30, 8, C.byref(geo), 0.1, 0.1, 0.0, 0.0, float("nan"), None,
                                      C.byref(opt), C.byref(h))
         assert rc == axlb.EINVAL and not h.value
+
+
+def test_slab_row_and_whole_member_arguments_are_checked():
+    """A negative global row 0 is refused before any device call, and the
+    whole-member batch calls refuse a NULL batch."""
+    import ctypes as C
+    from paper_1806_10241_amd import axlb
+    lib = axlb.load()
+    geo = axlb.Geometry(axlb.ANNULUS, 10.0)
+    opt = axlb.Options()
+    opt.layout, opt.T_ref, opt.device, opt.row0 = axlb.LAYOUT_AB, 0.5, 0, -1
+    h = C.c_void_p()
+    rc = lib.axlb_lattice_create(30, 8, C.byref(geo), 0.1, 0.1, 0.0, 0.0, float("nan"), None,
+                                 C.byref(opt), C.byref(h))
+    assert rc == axlb.EINVAL and not h.value and b"row0" in lib.axlb_last_error(None)
+    assert lib.axlb_batch_set_whole(None, 100) == axlb.EINVAL
+    m, k = C.c_longlong(), C.c_int()
+    assert lib.axlb_batch_get_whole(None, C.byref(m), C.byref(k)) == axlb.EINVAL
