@@ -53,8 +53,9 @@ extern "C" {
  * the slot, so that a run (and a checkpoint replay) is deterministic.
  * bfloat16 with lagged derivatives stores each population minus its linear
  * equilibrium part (3 w_q e_q.u for f, w_q u_theta for g, w_q (T - T_ref)
- * for h) taken at the lagged fields of the node that wrote it; a checkpoint
- * image of such a lattice loads only into another one. */
+ * for h) taken at the lagged fields of the node that wrote it, so bfloat16
+ * takes the lagged derivatives only (AXLB_DERIV_LAGGED); its checkpoint
+ * images carry a magic of their own. */
 
 /* ---- streaming layouts ---- */
 #define AXLB_LAYOUT_AA 0 /* one population buffer, in place, alternating phases */
@@ -79,7 +80,9 @@ extern "C" {
  *   layout allows, since in-place streaming overwrites a neighbour's
  *   current populations).
  * CURRENT: this step's output fields (after streaming, before the source
- *   half step) of the neighbours; needs AXLB_LAYOUT_AB.
+ *   half step) of the neighbours; needs AXLB_LAYOUT_AB and FP32 or binary16
+ *   storage (bfloat16 meets the 16-bit accuracy only through its offset
+ *   encoding, which takes the lagged fields: AXLB_EINVAL).
  * The two share every steady state. */
 #define AXLB_DERIV_LAGGED 0
 #define AXLB_DERIV_CURRENT 1

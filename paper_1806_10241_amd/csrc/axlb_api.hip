@@ -351,6 +351,10 @@ int axlb_lattice_create(int Nr, int Nz, const axlb_geometry *geo, double nu, dou
     if (O.deriv == AXLB_DERIV_CURRENT && O.layout != AXLB_LAYOUT_AB)
         return fail(nullptr, AXLB_EINVAL,
                     "current-step derivatives need the two-buffer, one-step layout");
+    if (O.deriv == AXLB_DERIV_CURRENT && O.storage == AXLB_BF16)
+        return fail(nullptr, AXLB_EINVAL,
+                    "bfloat16 storage needs the lagged derivatives: its offset encoding takes "
+                    "the lagged fields, and plain bfloat16 misses the 16-bit accuracy bar");
     if (!std::isfinite(O.T_ref)) return fail(nullptr, AXLB_EINVAL, "T_ref must be finite");
     if (O.row0 < 0 || (long long)O.row0 + Nz > INT32_MAX)
         return fail(nullptr, AXLB_EINVAL, "row0 must be >= 0 and row0 + Nz below 2^31");

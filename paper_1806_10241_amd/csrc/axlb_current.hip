@@ -7,8 +7,8 @@
 // its tile plus a one-node ring around it, keeps the four output fields of
 // all of them in LDS, and then differences from LDS.  The ring nodes are
 // streamed again by their own workgroups (reads that mostly hit L2); no
-// lagged-field buffer is read or written, and so the populations are stored
-// without the offset encoding of bfloat16 (which takes the lagged fields).
+// lagged-field buffer is read or written (and so this form takes FP32 or
+// binary16 storage, not the offset-encoded bfloat16).
 #include "axlb_device.h"
 #include "axlb_launch.h"
 #include "axlb_node.h"
@@ -149,14 +149,14 @@ static hipError_t fields_current_t(const KParams &P, const void *src, double *ou
 hipError_t launch_step_current(const KParams &P, int storage, int tile, const void *src,
                                void *dst, hipStream_t st) {
     if (storage == STORE_F16) return step_current_t<__half>(P, tile, src, dst, st);
-    if (storage == STORE_BF16) return step_current_t<__hip_bfloat16>(P, tile, src, dst, st);
+    if (storage == STORE_BF16) return hipErrorInvalidValue;  // refused at lattice creation
     return step_current_t<float>(P, tile, src, dst, st);
 }
 
 hipError_t launch_fields_current(const KParams &P, int storage, const void *src, double *out,
                                  hipStream_t st) {
     if (storage == STORE_F16) return fields_current_t<__half>(P, src, out, st);
-    if (storage == STORE_BF16) return fields_current_t<__hip_bfloat16>(P, src, out, st);
+    if (storage == STORE_BF16) return hipErrorInvalidValue;
     return fields_current_t<float>(P, src, out, st);
 }
 

@@ -90,6 +90,12 @@ def test_slab_row_and_whole_member_arguments_are_checked():
     rc = lib.axlb_lattice_create(30, 8, C.byref(geo), 0.1, 0.1, 0.0, 0.0, float("nan"), None,
                                  C.byref(opt), C.byref(h))
     assert rc == axlb.EINVAL and not h.value and b"row0" in lib.axlb_last_error(None)
+    # bfloat16 with current-step derivatives is refused before any device call
+    opt = axlb.Options()
+    opt.layout, opt.deriv, opt.storage, opt.T_ref, opt.device = axlb.LAYOUT_AB, 1, 2, 0.5, 0
+    rc = lib.axlb_lattice_create(30, 8, C.byref(geo), 0.1, 0.1, 0.0, 0.0, float("nan"), None,
+                                 C.byref(opt), C.byref(h))
+    assert rc == axlb.EINVAL and not h.value and b"bfloat16" in lib.axlb_last_error(None)
     assert lib.axlb_batch_set_whole(None, 100) == axlb.EINVAL
     m, k = C.c_longlong(), C.c_int()
     assert lib.axlb_batch_get_whole(None, C.byref(m), C.byref(k)) == axlb.EINVAL
