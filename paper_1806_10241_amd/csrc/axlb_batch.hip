@@ -60,20 +60,29 @@ __global__ void __launch_bounds__(BX *BY)
         const int local = t - d->tile_begin;
         const bool odd = (d->parity0 ^ phase) == 0;
         S *A = (S *)d->pop;
-        if (local < d->nedge) {  // edge nodes: their own entries in the odd phase only
+        // edge nodes have entries of their own in the odd phase and, with
+        // 16-bit storage, in the even phase too (as in the single-lattice
+        // kernel; with FP32 the even phase's extra edge entries cost more than
+        // the tiles' boundary code: 22.1k against 23.5k MLUPS on the 256
+        // uneven annuli)
+        constexpr bool SPLIT_EVEN = sizeof(S) == 2;
+        if (local < d->nedge) {
             const int e = local * (BX * BY) + (int)threadIdx.x;
-            if (!odd || e >= edge_count(d->P.Nr, d->P.Nz)) continue;
+            if ((!odd && !SPLIT_EVEN) || e >= edge_count(d->P.Nr, d->P.Nz)) continue;
             int i, j;
             edge_node(d->P, e, i, j);
-            update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j, false);
+            if (odd)
+                update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j, false);
+            else
+                update_node<S, MODE_AA_EVEN>(d->P, A, A, d->lag[1], d->lag[0], i, j, false);
             continue;
         }
         const int u = local - d->nedge;
         const int j = (u % d->gx) * BX + (int)threadIdx.x % BX;
         const int i = (u / d->gx) * BY + (int)threadIdx.x / BX;
-        if (odd) {
-            if (!interior_node(d->P, i, j)) continue;
-            update_planes<S>(d->P, d->pl[1], i, j, true);
+        if (odd || SPLIT_EVEN) {
+            if (!interior_node(d->P, i, j)) continue;  // edge nodes and the ragged tail
+            update_planes<S>(d->P, d->pl[odd ? 1 : 0], i, j, true);
         } else {
             if (i >= d->P.Nz || j >= d->P.Nr) continue;
             update_planes<S>(d->P, d->pl[0], i, j, interior_node(d->P, i, j));
@@ -112,7 +121,9 @@ static hipError_t launch_batch(int storage, int tile, int blocks, const InstDesc
 // one per workgroup, which takes the member through `nsteps` steps in one
 // launch (a bundle's 100 steps in one kernel) with a workgroup barrier
 // between steps: no launch per step, and the member's edge nodes run in the
-// same workgroup as its interior.  Every node of an AA phase reads and
+// same workgroup as its interior (the first threads take them, in both
+// phases, so that the interior loop runs the fast path alone: 15.1k against
+// 14.2k MLUPS on 1024 small annuli in FP32).  Every node of an AA phase reads and
 // writes only its own 19 slots, so the threads of a step need no order
 // among themselves; the barrier (with its workgroup-scope fences) makes a
 // step's stores visible to the next step's loads.  Thread k of the
@@ -133,20 +144,18 @@ __global__ void __launch_bounds__(WHOLE_THREADS)
         const int i0 = tid / Nr, j0 = tid % Nr;
         for (int s = 0; s < nsteps; ++s) {
             const bool odd = (d->parity0 ^ ((phase0 + s) & 1)) == 0;
-            if (odd) {
-                for (int e = tid; e < ne; e += WHOLE_THREADS) {
-                    int i, j;
-                    edge_node(d->P, e, i, j);
+            for (int e = tid; e < ne; e += WHOLE_THREADS) {
+                int i, j;
+                edge_node(d->P, e, i, j);
+                if (odd)
                     update_node<S, MODE_AA_ODD>(d->P, A, A, d->lag[0], d->lag[1], i, j, false);
-                }
+                else
+                    update_node<S, MODE_AA_EVEN>(d->P, A, A, d->lag[1], d->lag[0], i, j, false);
             }
             int i = i0, j = j0;
+            const Planes &pl = d->pl[odd ? 1 : 0];
             for (int k = tid; k < N; k += WHOLE_THREADS) {
-                if (odd) {
-                    if (interior_node(d->P, i, j)) update_planes<S>(d->P, d->pl[1], i, j, true);
-                } else {
-                    update_planes<S>(d->P, d->pl[0], i, j, interior_node(d->P, i, j));
-                }
+                if (interior_node(d->P, i, j)) update_planes<S>(d->P, pl, i, j, true);
                 i += di;
                 j += dj;
                 if (j >= Nr) {
