@@ -551,7 +551,7 @@ def main():
     ap.add_argument("--Nz", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=20,
                     help="steps of the oracle on one thread on the benchmark lattice")
-    ap.add_argument("--cpu-steps-all", type=int, default=100,
+    ap.add_argument("--cpu-steps-all", type=int, default=300,
                     help="steps of the oracle on every core on the benchmark lattice")
     ap.add_argument("--u-noise", type=float, default=1e-4,
                     help="seeded velocity noise of the initial state (0: at rest, so that "
